@@ -1,0 +1,88 @@
+"""MI355X (gfx950) 4-bit X-engine: cross-correlation of Excess-8 complex samples.
+
+Thin Python binding over the C ABI in include/xengine.h. Every step of the
+correlation runs in the library's HIP kernels; this module only checks tensor
+types and passes device pointers and the current HIP stream. PyTorch provides
+device memory and streams.
+
+    x   = torch.uint8  [F][T][N] on the GPU  (high nibble Re+8, low nibble Im+8)
+    vis = torch.int32  [F][N(N+1)/2][2]      (re, im), row-major upper triangle
+    correlate(x, vis)                         # V_ij = sum_t x_i(t) conj(x_j(t))
+"""
+from __future__ import annotations
+
+from . import metrics
+from ._lib import XengError, check, lib
+
+__all__ = ["correlate", "correlate_variant", "new_vis", "vis_entries", "tri_index",
+           "tile_count", "variants", "XengError", "metrics", "MAX_SAMPLES"]
+
+MAX_SAMPLES = metrics.MAX_SAMPLES
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes_void(stream.cuda_stream)
+
+
+def ctypes_void(v):
+    import ctypes
+    return ctypes.c_void_p(int(v))
+
+
+def _check_tensors(x, vis):
+    import torch
+    if x.dtype != torch.uint8 or x.dim() != 3:
+        raise TypeError("x must be a uint8 tensor [F][T][N]")
+    if vis.dtype != torch.int32:
+        raise TypeError("vis must be an int32 tensor [F][N(N+1)/2][2]")
+    if not (x.is_cuda and vis.is_cuda):
+        raise TypeError("x and vis must be GPU tensors (the library has no CPU path)")
+    if not x.is_contiguous() or not vis.is_contiguous():
+        raise TypeError("x and vis must be contiguous")
+    f, t, n = x.shape
+    if vis.numel() != 2 * f * vis_entries(n):
+        raise ValueError("vis must hold F*N(N+1)/2 (re, im) pairs")
+    return f, t, n
+
+
+def correlate(x, vis, t_prev: int = 0, accumulate: bool = False, stream=None):
+    """Correlate x into vis on the GPU (enqueued on ``stream``, default current)."""
+    f, t, n = _check_tensors(x, vis)
+    check(lib().xeng_correlate(x.data_ptr() if t else None, vis.data_ptr(), n, f, t, int(t_prev),
+                               int(bool(accumulate)), _stream_ptr(stream)))
+    return vis
+
+
+def correlate_variant(x, vis, variant: int, split_t: int = 1, t_prev: int = 0,
+                      accumulate: bool = False, stream=None):
+    """Same as correlate() with an explicit kernel variant and time split."""
+    f, t, n = _check_tensors(x, vis)
+    check(lib().xeng_correlate_variant(x.data_ptr() if t else None, vis.data_ptr(), n, f, t,
+                                       int(t_prev), int(bool(accumulate)), int(variant),
+                                       int(split_t), _stream_ptr(stream)))
+    return vis
+
+
+def new_vis(n: int, f: int, device="cuda"):
+    import torch
+    return torch.zeros((f, vis_entries(n), 2), dtype=torch.int32, device=device)
+
+
+def vis_entries(n: int) -> int:
+    return int(lib().xeng_vis_entries(int(n)))
+
+
+def tri_index(n: int, i: int, j: int) -> int:
+    return int(lib().xeng_tri_index(int(n), int(i), int(j)))
+
+
+def tile_count(n: int, tile: int) -> int:
+    return int(lib().xeng_tile_count(int(n), int(tile)))
+
+
+def variants():
+    L = lib()
+    return [L.xeng_variant_name(k).decode() for k in range(L.xeng_variant_count())]

@@ -1,0 +1,21 @@
+// xcorr_launch.h -- host-side launchers of the correlation kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xeng {
+
+// Zero `pairs` int32 pairs starting at vis (a fill kernel, so it is also safe
+// to record into a captured graph).
+hipError_t launch_fill_zero(int32_t* vis, int64_t pairs, hipStream_t stream);
+
+// 128x128-tile MFMA kernel. split > 1 divides the time axis among that many
+// workgroups per tile and combines them with int32 atomic adds; the caller
+// zero-fills vis first when not accumulating. aligned = (n % 4 == 0 and the
+// input base is 4-byte aligned), which enables dword loads.
+hipError_t launch_tile128(const uint8_t* in, int32_t* vis, int n, int f, int t, int accumulate,
+                          int split, bool aligned, hipStream_t stream);
+int tile128_stage_samples();
+
+}  // namespace xeng

@@ -1,0 +1,134 @@
+// xengine.cpp -- the C ABI declared in include/xengine.h: argument checks,
+// error reporting and dispatch to the gfx950 kernels.
+#include "xengine.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "xcorr_launch.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+xeng_status fail(xeng_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+xeng_status fail(xeng_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+xeng_status device_fail(hipError_t err, const char* what) {
+  return fail(XENG_EDEVICE, "%s: %s", what, hipGetErrorString(err));
+}
+
+struct Variant {
+  const char* name;
+};
+
+const Variant kVariants[] = {
+    {"tile128_kc64_mfma32x32x32"},
+};
+constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return na && nb && a0 < b0 + nb && b0 < a0 + na;
+}
+
+// Shared validation of one correlation job; fills byte counts on success.
+xeng_status check_job(const uint8_t* d_in, const int32_t* d_vis, int n, int f, int t,
+                      int64_t t_prev, int accumulate, size_t* in_bytes, size_t* vis_bytes) {
+  if (n < 1 || f < 1 || t < 0)
+    return fail(XENG_EINVAL, "need n >= 1, f >= 1, t >= 0 (got n=%d f=%d t=%d)", n, f, t);
+  if (accumulate != 0 && accumulate != 1)
+    return fail(XENG_EINVAL, "accumulate must be 0 or 1 (got %d)", accumulate);
+  if (t_prev < 0 || (!accumulate && t_prev != 0))
+    return fail(XENG_EINVAL, "t_prev must be >= 0, and 0 when not accumulating (got %lld)",
+                (long long)t_prev);
+  if (t_prev + (int64_t)t > XENG_MAX_SAMPLES)
+    return fail(XENG_ERANGE, "t_prev + t = %lld exceeds %lld samples: int32 sums could overflow",
+                (long long)(t_prev + t), (long long)XENG_MAX_SAMPLES);
+  const unsigned __int128 ib = (unsigned __int128)f * (unsigned)t * (unsigned)n;
+  const unsigned __int128 entries = (unsigned __int128)n * (n + 1) / 2;
+  const unsigned __int128 vb = entries * (unsigned)f * 8u;
+  if (ib > ((unsigned __int128)1 << 62) || vb > ((unsigned __int128)1 << 62))
+    return fail(XENG_EINVAL, "problem size overflows the address space");
+  if (d_vis == nullptr) return fail(XENG_EINVAL, "d_vis is NULL");
+  if (t > 0 && d_in == nullptr) return fail(XENG_EINVAL, "d_in is NULL");
+  if (((uintptr_t)d_vis) % 8 != 0) return fail(XENG_EINVAL, "d_vis must be 8-byte aligned");
+  *in_bytes = (size_t)ib;
+  *vis_bytes = (size_t)vb;
+  if (t > 0 && ranges_overlap(d_in, *in_bytes, d_vis, *vis_bytes))
+    return fail(XENG_EINVAL, "d_in and d_vis overlap");
+  return XENG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* xeng_last_error(void) { return g_last_error.c_str(); }
+
+const char* xeng_version(void) { return "xengine-gfx950 0.1.0"; }
+
+int64_t xeng_vis_entries(int n) { return n < 0 ? -1 : (int64_t)n * (n + 1) / 2; }
+
+int64_t xeng_tri_index(int n, int i, int j) {
+  if (n < 1 || i < 0 || j < i || j >= n) return -1;
+  return (int64_t)i * (2 * (int64_t)n - i + 1) / 2 + (j - i);
+}
+
+int64_t xeng_tile_count(int n, int tile) {
+  if (n < 1 || tile < 1) return -1;
+  const int64_t nb = ((int64_t)n + tile - 1) / tile;
+  return nb * (nb + 1) / 2;
+}
+
+int xeng_variant_count(void) { return kVariantCount; }
+
+const char* xeng_variant_name(int variant) {
+  return (variant >= 0 && variant < kVariantCount) ? kVariants[variant].name : nullptr;
+}
+
+xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
+                                   int64_t t_prev, int accumulate, int variant, int split_t,
+                                   void* hip_stream) {
+  size_t in_bytes = 0, vis_bytes = 0;
+  xeng_status st = check_job(d_in, d_vis, n, f, t, t_prev, accumulate, &in_bytes, &vis_bytes);
+  if (st != XENG_OK) return st;
+  if (variant < -1 || variant >= kVariantCount)
+    return fail(XENG_ENOTFOUND, "unknown kernel variant %d", variant);
+  if (split_t < 0) return fail(XENG_EINVAL, "split_t must be >= 0 (0 = choose)");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  const int64_t pairs = (int64_t)(vis_bytes / 8);
+  if (t == 0) {
+    if (accumulate) return XENG_OK;
+    hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
+    return e == hipSuccess ? XENG_OK : device_fail(e, "zero fill");
+  }
+  int split = split_t > 0 ? split_t : 1;
+  const bool aligned = (n % 4 == 0) && ((uintptr_t)d_in % 4 == 0);
+  if (split > 1 && !accumulate) {
+    hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
+    if (e != hipSuccess) return device_fail(e, "zero fill");
+  }
+  hipError_t e = xeng::launch_tile128(d_in, d_vis, n, f, t, accumulate, split, aligned, stream);
+  if (e != hipSuccess) return device_fail(e, "correlation kernel launch");
+  return XENG_OK;
+}
+
+xeng_status xeng_correlate(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
+                           int64_t t_prev, int accumulate, void* hip_stream) {
+  return xeng_correlate_variant(d_in, d_vis, n, f, t, t_prev, accumulate, -1, 0, hip_stream);
+}
+
+}  // extern "C"

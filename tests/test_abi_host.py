@@ -1,0 +1,102 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and its index helpers and argument checks behave as
+documented. No call here reaches the GPU: every correlate call below is
+rejected by the argument checks before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xengine.h")
+
+EINVAL, ERANGE, ENOTFOUND = -1, -2, -6
+FAKE_IN = 0x10000000
+FAKE_VIS = 0x20000000
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xeng_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1503_06203_amd import _lib
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1503_06203_amd import _lib
+    names = declared_functions()
+    assert "xeng_correlate" in names
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, "binding lacks " + name
+
+
+def test_tri_index_is_row_major_bijection(lib):
+    for n in (1, 2, 3, 7, 64, 129):
+        i, j = np.triu_indices(n)
+        ks = [lib.xeng_tri_index(n, int(a), int(b)) for a, b in zip(i, j)]
+        assert ks == list(range(n * (n + 1) // 2))
+        assert lib.xeng_vis_entries(n) == n * (n + 1) // 2
+    assert lib.xeng_tri_index(4, 2, 1) == -1
+    assert lib.xeng_tri_index(4, 0, 4) == -1
+    assert lib.xeng_tri_index(4, -1, 0) == -1
+    big = 46341  # entries exceed 2^31
+    assert lib.xeng_tri_index(big, big - 1, big - 1) == big * (big + 1) // 2 - 1
+
+
+def test_tile_count_fig1(lib):
+    assert lib.xeng_tile_count(256, 32) == 36      # Fig. 1
+    assert lib.xeng_tile_count(2048, 128) == 136
+    assert lib.xeng_tile_count(257, 128) == 6
+    assert lib.xeng_tile_count(0, 32) == -1
+
+
+def call(lib, n=16, f=1, t=8, t_prev=0, acc=0, d_in=FAKE_IN, d_vis=FAKE_VIS, variant=0, split=1):
+    return lib.xeng_correlate_variant(d_in, d_vis, n, f, t, t_prev, acc, variant, split, None)
+
+
+def test_rejects_bad_shapes(lib):
+    assert call(lib, n=0) == EINVAL
+    assert call(lib, f=0) == EINVAL
+    assert call(lib, t=-1) == EINVAL
+    assert "n >= 1" in lib.xeng_last_error().decode()
+    assert call(lib, acc=2) == EINVAL
+    assert call(lib, d_vis=None) == EINVAL
+    assert call(lib, d_in=None) == EINVAL
+    assert call(lib, d_vis=FAKE_VIS + 4) == EINVAL        # not 8-byte aligned
+    assert call(lib, split=-1) == EINVAL
+
+
+def test_rejects_overlap(lib):
+    # input [1][8][16] = 128 bytes; output starts inside it
+    assert call(lib, d_vis=FAKE_IN + 64) == EINVAL
+    assert "overlap" in lib.xeng_last_error().decode()
+
+
+def test_range_guard(lib):
+    m = 16_777_215
+    assert call(lib, t=8, t_prev=m - 7, acc=1) == ERANGE
+    assert call(lib, t=8, t_prev=5, acc=0) == EINVAL      # t_prev only when accumulating
+    assert call(lib, t=8, t_prev=-1, acc=1) == EINVAL
+
+
+def test_unknown_variant(lib):
+    assert call(lib, variant=lib.xeng_variant_count()) == ENOTFOUND
+    assert lib.xeng_variant_name(-5) is None
+    assert lib.xeng_variant_name(0) is not None
+
+
+def test_python_binding_errors_without_gpu():
+    import torch
+    import paper_1503_06203_amd as xe
+    x = torch.zeros((1, 4, 4), dtype=torch.uint8)
+    v = torch.zeros((1, 10, 2), dtype=torch.int32)
+    with pytest.raises(TypeError):
+        xe.correlate(x, v)            # CPU tensors: there is no CPU path

@@ -1,0 +1,141 @@
+"""Bit-exact parity of the HIP path against the CPU oracle (tolerance 0).
+
+Every input is seeded and synthetic. Small shapes are checked in full; the
+full-size workloads are checked on every entry among a set of elements that
+straddles every tile boundary (sub-matrix property: V_ij depends only on
+elements i and j), plus full oracle channels where that is cheap."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from synth import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+from gpu_helpers import (assert_same, boundary_elements, gather_subset, gpu_correlate,  # noqa: E402
+                         subset_reference)
+
+
+def full_check(x_cpu, **kw):
+    vis = gpu_correlate(x_cpu.to(DEV), **kw)
+    assert_same(vis, oracle.correlate(x_cpu.numpy()), str(tuple(x_cpu.shape)))
+
+
+def test_tiny_workload():
+    w = workloads.TINY
+    x = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, w.seed)
+    full_check(x)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 17, 31, 33, 64, 100, 127, 128, 129, 255, 256, 257])
+def test_element_tails(n):
+    x = synth.uniform_bytes(2, 97, n, seed=n)
+    full_check(x)
+
+
+@pytest.mark.parametrize("t", [1, 2, 15, 16, 17, 31, 33, 63, 64, 65, 127, 129, 4097])
+def test_time_tails(t):
+    x = synth.quantized_gaussian(1, t, 160, 3.0, seed=t)
+    full_check(x)
+
+
+def test_empty_time_axis_zero_fills_and_accumulate_is_noop():
+    import paper_1503_06203_amd as xe
+    x = torch.zeros((2, 0, 40), dtype=torch.uint8, device=DEV)
+    vis = torch.full((2, xe.vis_entries(40), 2), 7, dtype=torch.int32, device=DEV)
+    xe.correlate(x, vis, accumulate=True, t_prev=3)
+    torch.cuda.synchronize()
+    assert (vis == 7).all()
+    xe.correlate(x, vis)
+    torch.cuda.synchronize()
+    assert (vis == 0).all()
+
+
+@pytest.mark.parametrize("byte,re", [(0x00, 128), (0xFF, 98), (0x88, 0), (0x80, 64)])
+def test_constant_extremes(byte, re):
+    # closed form T*(a^2 + b^2): 0x00 = (-8,-8) -> 128, 0xFF = (7,7) -> 98, 0x80 = (0,-8) -> 64
+    t = 1000
+    x = synth.constant_bytes(3, t, 200, byte, device=DEV)
+    vis = gpu_correlate(x).cpu().numpy()
+    assert (vis[..., 0] == re * t).all() and (vis[..., 1] == 0).all()
+
+
+def test_accumulate_frames_equals_one_long_frame():
+    x = synth.quantized_gaussian(2, 600, 150, 2.5, seed=9)
+    xd = x.to(DEV)
+    whole = gpu_correlate(xd)
+    first = gpu_correlate(xd[:, :250].contiguous())
+    both = gpu_correlate(xd[:, 250:].contiguous(), prev=first, t_prev=250)
+    assert torch.equal(whole, both)
+    assert_same(both, oracle.correlate(x.numpy()))
+
+
+@pytest.mark.parametrize("split", [2, 3, 7, 64])
+def test_time_split_bit_identical(split):
+    x = synth.quantized_gaussian(2, 1000, 300, 2.5, seed=split)
+    xd = x.to(DEV)
+    ref = gpu_correlate(xd, variant=0, split=1)
+    got = gpu_correlate(xd, variant=0, split=split)
+    assert torch.equal(ref, got)
+    prev = torch.randint(-1000, 1000, ref.shape, dtype=torch.int32, device=DEV)
+    got2 = gpu_correlate(xd, variant=0, split=split, prev=prev.clone(), t_prev=10)
+    assert torch.equal(got2, ref + prev)
+
+
+def test_repeat_runs_bit_identical():
+    x = synth.uniform_bytes(4, 512, 384, seed=5, device=DEV)
+    a = gpu_correlate(x)
+    b = gpu_correlate(x)
+    assert torch.equal(a, b)
+
+
+def test_unaligned_input_pointer():
+    # input starting one byte into an allocation: the byte-load path
+    x = synth.uniform_bytes(1, 1 * 130 * 64 + 1, 1, seed=3).reshape(-1)
+    body = x[1:].reshape(1, 130, 64)
+    xd = torch.empty(x.numel(), dtype=torch.uint8, device=DEV)
+    xd.copy_(x.to(DEV))
+    view = xd[1:].view(1, 130, 64)
+    assert view.data_ptr() % 4 == 1
+    vis = gpu_correlate(view)
+    assert_same(vis, oracle.correlate(body.numpy()))
+
+
+def test_pathfinder_full_size():
+    # N=256, F=256, T=16384, sigma 2.5 with a 0.3 common component
+    w = workloads.PATHFINDER
+    xd = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, w.seed, common=w.common, device=DEV)
+    vis = gpu_correlate(xd)
+    x = xd.cpu().numpy()
+    for ch in (0, w.f - 1):
+        assert_same(vis[ch:ch + 1], oracle.correlate(x[ch:ch + 1]), "channel %d" % ch)
+    elems = boundary_elements(w.n, extra=16)
+    assert_same(gather_subset(vis, w.n, elems), subset_reference(x, elems), "subset")
+
+
+def test_large_n_four_frames_accumulated():
+    # N=2048, F=16, T=65536 per frame, sigma 3, 4 frames summed on the device
+    w = workloads.LARGE_N
+    elems = boundary_elements(w.n, extra=8, offsets=(-1, 0))
+    vis = None
+    want = None
+    for k, seed in enumerate(w.seeds()):
+        xd = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, seed, device=DEV)
+        vis = gpu_correlate(xd, prev=vis, t_prev=k * w.t)
+        sub = xd[:, :, torch.as_tensor(elems, device=DEV)].cpu().numpy()
+        part = oracle.correlate(sub)
+        want = part if want is None else want + part
+        del xd
+    assert_same(gather_subset(vis, w.n, elems), want, "large-N subset")
