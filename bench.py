@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the 4-bit X-engine hot path on one MI355X.
+
+A step is one full correlation of one batch of synthetic input that is already
+resident in HBM: for the default workload (CHIME Pathfinder shape, N=256
+elements, F=256 channels, T=16384 samples) one call of the library over the
+whole [F][T][N] block. Prints ONE JSON line:
+
+  value       effective correlation TOPS = 8 * N(N+1)/2 * F * T / step time
+              (paper Eq. 2 operation count; redundant work is never counted)
+  roofline    the correlation kernel against the int8 MFMA peak, timed with
+              HIP events on the stream it is launched on
+  cpu_baseline the CPU oracle timed on a bounded sample of the same workload
+  secondary   the same measurement on the large-N workload (N=2048, F=16,
+              T=65536 per frame, 4 frames accumulated on the device)
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_INT8_TOPS = 5000.0      # MI355X dense int8 MFMA, TOP/s
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1503_06203_amd", "csrc", "*"))):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload: str, digest: str):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+    counters, as recorded in profiles/, if taken on the current kernel source."""
+    pat = re.compile(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)\s+workload:\s*(\S+)\s+"
+                     r"kernel_source:\s*([0-9a-f]+)")
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            m = pat.search(line)
+            if m and m.group(2) == workload and m.group(3) == digest:
+                return float(m.group(1))
+    return None
+
+
+def time_steps(step, steps: int, warmup: int):
+    """Time `steps` calls of step() after `warmup` untimed ones.
+
+    Returns (wall seconds for all steps, per-launch kernel seconds from HIP
+    events recorded on the current stream around each launch)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        step()
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [s.elapsed_time(e) / 1e3 for s, e in zip(starts, ends)]
+    return wall, per
+
+
+def bench_workload(w, steps: int, warmup: int):
+    import torch
+
+    import paper_1503_06203_amd as xe
+    import synth
+    from paper_1503_06203_amd import metrics
+
+    dev = "cuda:0"
+    frames = [synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, s, common=w.common, device=dev)
+              for s in w.seeds()]
+    vis = xe.new_vis(w.n, w.f, device=dev)
+    state = {"k": 0}
+
+    def step():
+        # one frame per step; frames after the first add to the resident sums
+        k = state["k"]
+        x = frames[k % len(frames)]
+        first = (k % len(frames)) == 0
+        xe.correlate(x, vis, t_prev=0 if first else (k % len(frames)) * w.t, accumulate=not first)
+        state["k"] = k + 1
+
+    torch.cuda.synchronize()
+    wall, per = time_steps(step, steps, warmup)
+    ops = metrics.effective_ops(w.n, w.f, w.t)
+    step_s = wall / steps
+    kern_s = sum(per) / len(per)
+    del frames
+    torch.cuda.empty_cache()
+    return {
+        "value": ops / step_s / 1e12,
+        "ms_per_step": step_s * 1e3,
+        "kernel_ms": kern_s * 1e3,
+        "kernel_tops": ops / kern_s / 1e12,
+        "ops_per_step": ops,
+        "input_bytes": metrics.input_bytes(w.n, w.f, w.t),
+    }
+
+
+def cpu_baseline(w, budget_s: float = 15.0):
+    """Time the CPU oracle on the first k channels of the workload (all N
+    elements and T samples), k chosen from a one-channel calibration so the
+    timed run takes about budget_s."""
+    import numpy as np
+
+    import oracle
+    import synth
+    from paper_1503_06203_amd import metrics
+
+    oracle.build(force=False)
+    n_elems = w.n
+    if metrics.effective_ops(w.n, 1, w.t) > 2e12:       # one channel is too much: shrink N
+        n_elems = 256
+
+    def draw(k):
+        x = synth.quantized_gaussian(k, w.t, w.n, w.sigma, w.seeds()[0], common=w.common)
+        return np.ascontiguousarray(x.numpy()[:, :, :n_elems])
+
+    one_ch = draw(1)
+    t0 = time.perf_counter()
+    oracle.correlate(one_ch)
+    one = time.perf_counter() - t0
+    k = int(max(1, min(w.f, budget_s / max(one, 1e-3))))
+    sample = draw(k)
+    t0 = time.perf_counter()
+    oracle.correlate(sample)
+    dt = time.perf_counter() - t0
+    ops = metrics.effective_ops(n_elems, k, w.t)
+    return {"value": ops / dt / 1e12, "unit": "TOPS", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%d of %d channels, N=%d, T=%d (%.3g effective ops in %.2f s)"
+                      % (k, w.f, n_elems, w.t, ops, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="pathfinder", choices=["tiny", "pathfinder", "large_n"])
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (frequency "
+              "channels would shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        sys.exit(2)
+    from synth import workloads
+
+    w = workloads.WORKLOADS[args.workload]
+    r = bench_workload(w, args.steps, args.warmup)
+    digest = kernel_source_digest()
+    traffic = recorded_traffic(w.name, digest)
+    line = {
+        "metric": "effective correlation TOPS (8 ops/complex MAC) + % int8 MFMA peak",
+        "value": round(r["value"], 3),
+        "unit": "TOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "f": w.f, "t": w.t, "sigma": w.sigma,
+                   "common": w.common, "frames": len(w.seeds()), "input": "uint8[F][T][N] 4+4-bit",
+                   "output": "int32[F][N(N+1)/2][2]", "parallelism": "single-gpu"},
+        "pct_int8_peak": round(100 * r["value"] / PEAK_INT8_TOPS, 2),
+        "roofline": {
+            "bound": "mfma",
+            "achieved": round(r["kernel_tops"], 3),
+            "peak": PEAK_INT8_TOPS,
+            "unit": "TOP/s",
+            "frac": round(r["kernel_tops"] / PEAK_INT8_TOPS, 4),
+            "traffic": traffic,
+            "kernel": "xcorr_tile128_kernel",
+            "kernel_ms": round(r["kernel_ms"], 5),
+            "algorithmic_ops_per_launch": r["ops_per_step"],
+            "input_gbs": round(r["input_bytes"] / (r["kernel_ms"] / 1e3) / 1e9, 1),
+            "kernel_source": digest,
+        },
+    }
+    if not args.no_secondary and w.name != "large_n":
+        lw = workloads.LARGE_N
+        s = bench_workload(lw, 8, 2)
+        line["secondary"] = {"workload": lw.name, "n": lw.n, "f": lw.f, "t": lw.t,
+                             "frames": len(lw.seeds()), "value": round(s["value"], 3),
+                             "unit": "TOPS", "ms_per_step": round(s["ms_per_step"], 4),
+                             "kernel_tops": round(s["kernel_tops"], 3),
+                             "frac_int8_peak": round(s["kernel_tops"] / PEAK_INT8_TOPS, 4)}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

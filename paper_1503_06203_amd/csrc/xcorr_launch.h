@@ -18,4 +18,13 @@ hipError_t launch_tile128(const uint8_t* in, int32_t* vis, int n, int f, int t, 
                           int split, bool aligned, hipStream_t stream);
 int tile128_stage_samples();
 
+// 128x256-tile MFMA kernel, one workgroup per CU. Needs n % 4 == 0 and a
+// 4-byte aligned input (dword buffer loads). Sums samples [t0, t0 + t_count)
+// of each channel (t = samples per channel); t_count is limited to
+// wide_max_samples_per_launch() so the scaled int32 sums cannot overflow.
+hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
+                       int accumulate, int split, hipStream_t stream);
+int64_t wide_max_samples_per_launch();
+int64_t wide_tiles_per_channel(int n);
+
 }  // namespace xeng

@@ -139,3 +139,42 @@ def test_large_n_four_frames_accumulated():
         want = part if want is None else want + part
         del xd
     assert_same(gather_subset(vis, w.n, elems), want, "large-N subset")
+
+
+VARIANT_SHAPES = [(1, 64, 4), (2, 97, 128), (1, 200, 256), (2, 333, 260), (1, 1000, 384),
+                  (1, 130, 512), (3, 64, 132), (1, 4097, 256), (2, 1, 1024)]
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("f,t,n", VARIANT_SHAPES)
+def test_each_variant_matches_oracle(variant, f, t, n):
+    x = synth.quantized_gaussian(f, t, n, 3.0, seed=f * 7919 + t * 31 + n)
+    full_check(x, variant=variant, split=1)
+
+
+@pytest.mark.parametrize("split", [2, 5])
+def test_wide_variant_time_split(split):
+    x = synth.quantized_gaussian(1, 1500, 512, 2.5, seed=split + 40)
+    xd = x.to(DEV)
+    ref = gpu_correlate(xd, variant=0, split=1)
+    got = gpu_correlate(xd, variant=1, split=split)
+    assert torch.equal(ref, got)
+    assert_same(got, oracle.correlate(x.numpy()))
+
+
+def test_long_integration_windows():
+    # T above one launch window of the wide kernel (2^20 - 64 samples)
+    x = synth.quantized_gaussian(1, 1_100_000, 64, 2.5, seed=77)
+    full_check(x)
+
+
+def test_int32_boundary_on_gpu():
+    # T = 16 777 215 samples of (-8,-8): Re = 128*T = 2 147 483 520, the int32 limit
+    import paper_1503_06203_amd as xe
+    t = xe.MAX_SAMPLES
+    x = torch.zeros((1, t, 8), dtype=torch.uint8, device=DEV)
+    vis = gpu_correlate(x).cpu().numpy()
+    assert (vis[..., 0] == 128 * t).all() and (vis[..., 1] == 0).all()
+    v2 = xe.new_vis(8, 1, device=DEV)
+    with pytest.raises(xe.XengError):
+        xe.correlate(x[:, :1].contiguous(), v2, t_prev=t, accumulate=True)
