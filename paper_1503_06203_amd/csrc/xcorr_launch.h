@@ -22,8 +22,9 @@ int tile128_stage_samples();
 // 4-byte aligned input (dword buffer loads). Sums samples [t0, t0 + t_count)
 // of each channel (t = samples per channel); t_count is limited to
 // wide_max_samples_per_launch() so the scaled int32 sums cannot overflow.
+// waves = 4 (one wave of 64x128 per SIMD) or 8 (two waves of 64x64 per SIMD).
 hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
-                       int accumulate, int split, hipStream_t stream);
+                       int accumulate, int split, int waves, hipStream_t stream);
 int64_t wide_max_samples_per_launch();
 int64_t wide_tiles_per_channel(int n);
 

@@ -4,22 +4,28 @@
 // Same contraction as the 128x128 kernel (paper Sec. II-A, Eq. 1 and 2):
 //   Re V_ij = P_i . P_j,  Im V_ij = Q_i . P_j,   P_e = [Re e, Im e],
 //   Q_e = [Im e, -Re e]  over the time axis,
-// on v_mfma_i32_32x32x32_i8. What changes is the shape, chosen for gfx950:
+// on v_mfma_i32_32x32x32_i8. The shape is chosen for gfx950:
 //   * a workgroup owns a 128 (rows, i) x 256 (columns, j) tile; each of the 4
 //     waves owns 64 x 128 = 2 x 4 blocks of 32x32, Re and Im: 256 int32
-//     accumulators per lane, one wave per SIMD. Larger tiles amortise the
-//     nibble decode (done once per staged byte) over more MFMA work.
+//     accumulators per lane, one wave per SIMD.
 //   * packed bytes are fetched with buffer loads whose row offset is a scalar
-//     register, so a load costs no vector ALU work; each wave fetches its own
-//     16-sample MFMA step of both panels, two stages ahead of use.
-//   * the decode of stage s+1 (transpose, Excess-8 -> int8, LDS write) is
-//     interleaved with the MFMA work of stage s.
+//     register (no vector ALU work per load), two stages ahead of use.
+//   * LDS traffic is the scarce resource (writes run at about half the read
+//     rate), so the two panels are staged differently:
+//       rows (A side, needs -Re): transposed and decoded once per workgroup
+//         into int8 slabs [Re g, Re g+1, Im g, Im g+1];
+//       columns (B side): stored raw, one byte per sample in the input's own
+//         [sample][element] order, and read with ds_read_b64_tr_b8, whose 8x8
+//         byte transpose hands each lane 8 consecutive samples of its own
+//         element; the lane then decodes them to 16 x [Re, Re', Im, Im'].
+//   * the decode of stage s+1 is interleaved with the MFMA work of stage s,
+//     and operand fragments are read one MFMA step ahead.
 //
 // K layout of one 16-sample step for element e, lane half h (0/1): the slab
-// [Re g, Re g+1, Im g, Im g+1] (g = 2h; each dword = 4 samples of one
-// component), plus a plane [-Re g, -Re g+1]. The Q operand is then
-// [Im g, Im g+1, -Re g, -Re g+1]: the slab's upper half followed by the plane,
-// which pairs sample by sample with P_j = [Re g, Re g+1, Im g, Im g+1].
+// [Re g, Re g+1, Im g, Im g+1] with g = 2h (each dword = 4 consecutive samples
+// of one component). Q is [Im g, Im g+1, -Re g, -Re g+1], which pairs sample by
+// sample with P_j. The B side carries 16x the sample values; every sum is an
+// exact multiple of 16 and the epilogue divides it out.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -37,10 +43,12 @@ constexpr int kCols = 256;            // tile columns (j, the P "B" side)
 constexpr int kThreads = 256;         // 4 waves, one per SIMD
 constexpr int kStage = 64;            // samples per LDS stage
 constexpr int kSteps = 4;             // 16-sample MFMA K steps per stage (= waves)
-constexpr int kColPBytes = kSteps * 2 * kCols * 16;
-constexpr int kRowPBytes = kSteps * 2 * kRows * 16;
-constexpr int kRowNaBytes = kSteps * 2 * kRows * 8;
-constexpr int kBufBytes = kColPBytes + kRowPBytes + kRowNaBytes;   // 56 KiB
+// Raw column panel: one row of kCols bytes per sample, padded so the eight
+// rows read by one 16-lane ds_read_b64_tr_b8 group fall on distinct banks.
+constexpr int kColRowStride = kCols + 32;
+constexpr int kColRawBytes = kStage * kColRowStride;                // 18 KiB
+constexpr int kRowPBytes = kSteps * 2 * kRows * 16;                 // 16 KiB
+constexpr int kBufBytes = kColRawBytes + kRowPBytes;
 constexpr uint32_t kOob = 0x80000000u;  // buffer offset past every record: load returns 0
 // The B operand carries 16x the sample value and one sample adds at most 128
 // to |Re|, so 16 * 128 * samples must stay below 2^31 within one launch.
@@ -107,46 +115,42 @@ __device__ inline void load_stage(Raw& raw, const uint8_t* chan, int n, int t0, 
   }
 }
 
-// Column (B) side: decode 8 raw rows (two 4-sample groups) of one quad and
-// write, per element, the slab [16 Re g, 16 Re g+1, 16 Im g, 16 Im g+1].
-// Scaling by 16 makes the decode two operations per dword: with u = w ^ 0x88
-// per nibble, u's high nibble is the 4-bit two's complement of Re, so
-// (u & 0xF0) is exactly 16*Re as a signed byte, and (u << 4) & 0xF0 is 16*Im.
-// Every product on the B side is then 16x; the epilogue divides exactly.
-__device__ inline void decode_cols(const uint32_t* rows8, uint8_t* pslab, int quad_base) {
-  uint32_t x0[4], x1[4];
-  transpose_4x4(rows8, x0);        // group g:   element k at samples 0..3
-  transpose_4x4(rows8 + 4, x1);    // group g+1
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int slot = slot_swizzle(quad_base + k);
-    const uint32_t u0 = x0[k] ^ kZeroSamples, u1 = x1[k] ^ kZeroSamples;
-    const v4i s = {(int)(u0 & 0xF0F0F0F0u), (int)(u1 & 0xF0F0F0F0u),
-                   (int)((u0 << 4) & 0xF0F0F0F0u), (int)((u1 << 4) & 0xF0F0F0F0u)};
-    *reinterpret_cast<v4i*>(pslab + slot * 16) = s;
-  }
-}
-
-// Row (A) side, unscaled: per element the slab [Re g, Re g+1, Im g, Im g+1]
-// and the plane [-Re g, -Re g+1]. Split in two halves (elements 0-1, 2-3) so
-// the work can be spread over two MFMA steps; x0/x1 carry the transposes.
+// Row (A) side: transpose 8 raw rows (two 4-sample groups) of one quad and
+// write, per element, the unscaled slab [Re g, Re g+1, Im g, Im g+1]. Split in
+// two halves (elements 0-1, 2-3) so the work spreads over two MFMA steps.
 __device__ inline void transpose_rows(const uint32_t* rows8, uint32_t x0[4], uint32_t x1[4]) {
   transpose_4x4(rows8, x0);
   transpose_4x4(rows8 + 4, x1);
 }
 __device__ inline void decode_rows_half(const uint32_t x0[4], const uint32_t x1[4], int part,
-                                        uint8_t* pslab, uint8_t* naslab, int quad_base) {
+                                        uint8_t* pslab, int quad_base) {
 #pragma unroll
   for (int kq = 0; kq < 2; ++kq) {
     const int k = 2 * part + kq;
     const int slot = slot_swizzle(quad_base + k);
-    const uint32_t h0 = fields_hi(x0[k]), h1 = fields_hi(x1[k]);
-    const v4i s = {(int)fields_to_s8(h0), (int)fields_to_s8(h1),
+    const v4i s = {(int)fields_to_s8(fields_hi(x0[k])), (int)fields_to_s8(fields_hi(x1[k])),
                    (int)fields_to_s8(fields_lo(x0[k])), (int)fields_to_s8(fields_lo(x1[k]))};
     *reinterpret_cast<v4i*>(pslab + slot * 16) = s;
-    const v2i na = {(int)fields_to_neg_s8(h0), (int)fields_to_neg_s8(h1)};
-    *reinterpret_cast<v2i*>(naslab + slot * 8) = na;
   }
+}
+
+// Column (B) side: 16 raw rows of the lane's quad go to LDS unchanged.
+__device__ inline void write_cols_raw(const uint32_t* rows16, uint8_t* dst) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    *reinterpret_cast<uint32_t*>(dst + r * kColRowStride) = rows16[r];
+}
+
+// 16 x [Re, Im] of four samples from four raw bytes. With u = w ^ 0x88 per
+// byte, u's high nibble is the 4-bit two's complement of Re, so u & 0xF0 is
+// exactly 16*Re as a signed byte, and (u << 4) & 0xF0 is 16*Im.
+__device__ inline uint32_t re16(uint32_t w) { return (w ^ kZeroSamples) & 0xF0F0F0F0u; }
+__device__ inline uint32_t im16(uint32_t w) { return ((w ^ kZeroSamples) << 4) & 0xF0F0F0F0u; }
+
+// Negated signed bytes in [-8, 7]: x ^ 0x7F + 1 stays below 0x100 per byte
+// (no carry), and flipping bit 7 turns the biased result back into -x.
+__device__ inline uint32_t neg_s8(uint32_t x) {
+  return ((x ^ 0x7F7F7F7Fu) + 0x01010101u) ^ 0x80808080u;
 }
 
 __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
@@ -188,15 +192,13 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
   const uint32_t voff_row = (uint32_t)row_e + (uint32_t)(8 * half) * (uint32_t)n;
   const bool panels_full = p.full_panels != 0;
 
-  // LDS destinations of this lane's decoded data
-  auto col_slab = [&](int buf, int h) {
-    return lds + buf * kBufBytes + ((wave * 2 + h) * kCols) * 16;
+  // LDS destinations of this lane's staged data: its 16 raw column rows
+  // (samples 16*wave.. of the stage, elements 4*lane..) and its row slabs
+  auto col_raw = [&](int buf) {
+    return lds + buf * kBufBytes + (wave * 16) * kColRowStride + 4 * lane;
   };
   auto row_slab = [&](int buf) {
-    return lds + buf * kBufBytes + kColPBytes + ((wave * 2 + half) * kRows) * 16;
-  };
-  auto row_na = [&](int buf) {
-    return lds + buf * kBufBytes + kColPBytes + kRowPBytes + ((wave * 2 + half) * kRows) * 8;
+    return lds + buf * kBufBytes + kColRawBytes + ((wave * 2 + half) * kRows) * 16;
   };
 
   auto fetch = [&](Raw& raw, int stage) {
@@ -221,13 +223,17 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
       active[rb][cb] = rs <= cs + 31 && rs < n && cs < n;
       wave_active |= active[rb][cb];
     }
-  int a_off[2], b_off[4];   // byte offsets of this lane's operand slots in a stage buffer
+  int a_off[2];   // slot index of this lane's A slabs within one K step
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
     a_off[rb] = (half * kRows + slot_swizzle(wr * 64 + rb * 32 + l32));
-#pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
-    b_off[cb] = (half * kCols + slot_swizzle(wc * 128 + cb * 32 + l32));
+  // ds_read_b64_tr_b8 addressing: in each 16-lane group the even lanes name
+  // the 8 sample rows of elements e0..e0+7 and the odd lanes those of
+  // e0+8..e0+15; lane k of the group receives element e0+k, 8 samples. Group
+  // g = (lane/16) covers elements 16*(g&1).. of the block, samples 8*(g>>1)..
+  const int grp = (lane >> 4) & 3;
+  const int b_off = ((grp >> 1) * 8 + ((lane & 15) >> 1)) * kColRowStride + wc * 128 +
+                    16 * (grp & 1) + 8 * (lane & 1);
 
   v16i acc_re[2][4], acc_im[2][4];
 #pragma unroll
@@ -238,34 +244,41 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
       acc_im[rb][cb] = v16i{};
     }
 
-  // Operand fragments of one 16-sample MFMA step.
+  // Operand fragments of one 16-sample MFMA step: A slabs (decoded) and B raw
+  // bytes (8 samples of this lane's column element per block).
   struct Frags {
     v4i pa[2];
-    v2i na[2];
-    v4i pb[4];
+    v2i rb[4];
   };
   auto load_frags = [&](Frags& fr, const uint8_t* base, int kk) {
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      fr.pa[rb] = *reinterpret_cast<const v4i*>(base + kColPBytes + (kk * 2 * kRows + a_off[rb]) * 16);
-      fr.na[rb] = *reinterpret_cast<const v2i*>(base + kColPBytes + kRowPBytes +
-                                                (kk * 2 * kRows + a_off[rb]) * 8);
-    }
+    for (int rb = 0; rb < 2; ++rb)
+      fr.pa[rb] = *reinterpret_cast<const v4i*>(base + kColRawBytes +
+                                                (kk * 2 * kRows + a_off[rb]) * 16);
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
-      fr.pb[cb] = *reinterpret_cast<const v4i*>(base + (kk * 2 * kCols + b_off[cb]) * 16);
+      fr.rb[cb] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+          (__attribute__((address_space(3))) v2i*)(base + b_off + kk * 16 * kColRowStride +
+                                                   cb * 32));
   };
   // All 8 blocks of the wave. Blocks lying below the diagonal are computed and
   // never stored: the busiest wave of the tile sets the stage time anyway.
   auto mfma_step = [&](const Frags& fr) {
+    v4i pb[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const uint32_t lo = (uint32_t)fr.rb[cb].x, hi = (uint32_t)fr.rb[cb].y;
+      pb[cb] = v4i{(int)re16(lo), (int)re16(hi), (int)im16(lo), (int)im16(hi)};
+    }
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
-      const v4i qa = {fr.pa[rb].z, fr.pa[rb].w, fr.na[rb].x, fr.na[rb].y};
+      const v4i qa = {fr.pa[rb].z, fr.pa[rb].w, (int)neg_s8((uint32_t)fr.pa[rb].x),
+                      (int)neg_s8((uint32_t)fr.pa[rb].y)};
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
         acc_re[rb][cb] =
-            __builtin_amdgcn_mfma_i32_32x32x32_i8(fr.pa[rb], fr.pb[cb], acc_re[rb][cb], 0, 0, 0);
-        acc_im[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(qa, fr.pb[cb], acc_im[rb][cb], 0, 0, 0);
+            __builtin_amdgcn_mfma_i32_32x32x32_i8(fr.pa[rb], pb[cb], acc_re[rb][cb], 0, 0, 0);
+        acc_im[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(qa, pb[cb], acc_im[rb][cb], 0, 0, 0);
       }
     }
   };
@@ -282,6 +295,18 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
     const uint8_t* base = lds + cur * kBufBytes;
     Frags f0, f1;
     uint32_t tx0[4], tx1[4];
+    // Order inside one MFMA step: the next step's LDS reads go out first, then
+    // each MFMA is followed by a few VALU ops (decode work), and the LDS
+    // writes of the decoded data come last.
+    auto pattern = []() {
+      __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);    // DS reads
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
+      }
+      __builtin_amdgcn_sched_group_barrier(0x200, 16, 0);   // DS writes
+    };
     __builtin_amdgcn_sched_barrier(0);
     load_frags(f0, base, 0);
     if (kFast)
@@ -292,22 +317,23 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
                        row_ok, half);
     __builtin_amdgcn_sched_barrier(0);
     load_frags(f1, base, 1);
-    if (kFast || do_dec) decode_cols(dec.col, col_slab(cur ^ 1, 0), 4 * lane);
+    if (kFast || do_dec) write_cols_raw(dec.col, col_raw(cur ^ 1));
     mfma_step(f0);
+    if (kFast) pattern();
     __builtin_amdgcn_sched_barrier(0);
     load_frags(f0, base, 2);
-    if (kFast || do_dec) decode_cols(dec.col + 8, col_slab(cur ^ 1, 1), 4 * lane);
+    if (kFast || do_dec) transpose_rows(dec.row, tx0, tx1);
     mfma_step(f1);
+    if (kFast) pattern();
     __builtin_amdgcn_sched_barrier(0);
     load_frags(f1, base, 3);
-    if (kFast || do_dec) {
-      transpose_rows(dec.row, tx0, tx1);
-      decode_rows_half(tx0, tx1, 0, row_slab(cur ^ 1), row_na(cur ^ 1), 4 * l32);
-    }
+    if (kFast || do_dec) decode_rows_half(tx0, tx1, 0, row_slab(cur ^ 1), 4 * l32);
     mfma_step(f0);
+    if (kFast) pattern();
     __builtin_amdgcn_sched_barrier(0);
-    if (kFast || do_dec) decode_rows_half(tx0, tx1, 1, row_slab(cur ^ 1), row_na(cur ^ 1), 4 * l32);
+    if (kFast || do_dec) decode_rows_half(tx0, tx1, 1, row_slab(cur ^ 1), 4 * l32);
     mfma_step(f1);
+    if (kFast) pattern();
     __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
   };
@@ -317,11 +343,10 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
   if (stage_begin + 1 < stage_end) fetch(rb_, stage_begin + 1);
   {
     uint32_t tx0[4], tx1[4];
-    decode_cols(ra.col, col_slab(0, 0), 4 * lane);
-    decode_cols(ra.col + 8, col_slab(0, 1), 4 * lane);
+    write_cols_raw(ra.col, col_raw(0));
     transpose_rows(ra.row, tx0, tx1);
-    decode_rows_half(tx0, tx1, 0, row_slab(0), row_na(0), 4 * l32);
-    decode_rows_half(tx0, tx1, 1, row_slab(0), row_na(0), 4 * l32);
+    decode_rows_half(tx0, tx1, 0, row_slab(0), 4 * l32);
+    decode_rows_half(tx0, tx1, 1, row_slab(0), 4 * l32);
   }
   __syncthreads();
   // Steady state, two stages per trip (buffers 0 and 1, register sets in
@@ -376,6 +401,271 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Two waves per SIMD: the same 128x256 tile, stage layout and LDS formats, but
+// 8 waves of 64x64 (2x2 blocks, 128 accumulators each). The two waves that
+// share a SIMD own the same 64 columns and complementary staging duties
+// (waves 0-3 decode the row panel of K step `wave`, waves 4-7 copy the raw
+// column panel of K step `wave-4`), so while one waits on memory or LDS the
+// other keeps the SIMD's matrix core busy.
+constexpr int kThreads8 = 512;
+
+struct Raw16 {
+  uint32_t w[16];
+};
+
+__global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
+  // With two waves per SIMD each wave has 256 registers. An AGPR operand here
+  // tells the compiler the kernel uses accumulation registers, so it splits
+  // them 128 VGPR + 128 AGPR and keeps the 128 accumulators out of the VGPRs.
+  asm volatile("; accumulators live in AGPRs" ::"a"(0));
+
+  const int logical = xcd_logical_id(blockIdx.x, gridDim.x);
+  const int tile = logical % p.ntiles;
+  const int rest = logical / p.ntiles;
+  const int split_idx = rest % p.split;
+  const int ch = rest / p.split;
+  int bj = 0, bi = tile;
+  while (true) {
+    const int cnt = min(2 * bj + 2, p.nbr);
+    if (bi < cnt) break;
+    bi -= cnt;
+    ++bj;
+  }
+  const int row0 = bi * kRows, col0 = bj * kCols;
+  const int stage_begin = split_idx * p.stages_per_split;
+  const int stage_end = min(stage_begin + p.stages_per_split, p.total_stages);
+  if (stage_begin >= stage_end) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int half = lane >> 5, l32 = lane & 31;
+  const int n = p.n;
+  const uint8_t* chan = p.in + (int64_t)ch * p.t * (int64_t)n;
+  const bool panels_full = p.full_panels != 0;
+  const int ks = wave & 3;               // K step this wave stages
+  const bool row_role = wave < 4;
+
+  // staging addresses
+  const int col_e = col0 + 4 * lane;
+  const int row_e = row0 + 4 * l32;
+  const bool col_ok = col_e < n, row_ok = row_e < n;
+  const uint32_t voff_col = (uint32_t)col_e;
+  const uint32_t voff_row = (uint32_t)row_e + (uint32_t)(8 * half) * (uint32_t)n;
+  uint8_t* const col_dst0 = lds + (ks * 16) * kColRowStride + 4 * lane;
+  uint8_t* const row_dst0 = lds + kColRawBytes + ((ks * 2 + half) * kRows) * 16;
+
+  // MFMA roles: rows 64*wr.., columns 64*wc..
+  const int wr = wave >> 2, wc = wave & 3;
+  bool wave_active = false;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int rs = row0 + wr * 64 + rb * 32, cs = col0 + wc * 64 + cb * 32;
+      wave_active |= rs <= cs + 31 && rs < n && cs < n;
+    }
+  int a_off[2];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+    a_off[rb] = (half * kRows + slot_swizzle(wr * 64 + rb * 32 + l32));
+  const int grp = (lane >> 4) & 3;
+  const int b_off = ((grp >> 1) * 8 + ((lane & 15) >> 1)) * kColRowStride + wc * 64 +
+                    16 * (grp & 1) + 8 * (lane & 1);
+
+  v16i acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      acc_re[rb][cb] = v16i{};
+      acc_im[rb][cb] = v16i{};
+    }
+
+  struct Frags {
+    v4i pa[2];
+    v2i rb[2];
+  };
+  auto load_frags = [&](Frags& fr, const uint8_t* base, int kk) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+      fr.pa[rb] = *reinterpret_cast<const v4i*>(base + kColRawBytes +
+                                                (kk * 2 * kRows + a_off[rb]) * 16);
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+      fr.rb[cb] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+          (__attribute__((address_space(3))) v2i*)(base + b_off + kk * 16 * kColRowStride +
+                                                   cb * 32));
+  };
+  auto mfma_step = [&](const Frags& fr) {
+    v4i pb[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const uint32_t lo = (uint32_t)fr.rb[cb].x, hi = (uint32_t)fr.rb[cb].y;
+      pb[cb] = v4i{(int)re16(lo), (int)re16(hi), (int)im16(lo), (int)im16(hi)};
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const v4i qa = {fr.pa[rb].z, fr.pa[rb].w, (int)neg_s8((uint32_t)fr.pa[rb].x),
+                      (int)neg_s8((uint32_t)fr.pa[rb].y)};
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        acc_re[rb][cb] =
+            __builtin_amdgcn_mfma_i32_32x32x32_i8(fr.pa[rb], pb[cb], acc_re[rb][cb], 0, 0, 0);
+        acc_im[rb][cb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(qa, pb[cb], acc_im[rb][cb], 0, 0, 0);
+      }
+    }
+  };
+
+  // Fetch this wave's share of one stage: row waves 8 rows of their row quad
+  // (half of K step ks), column waves 16 rows of their column quad.
+  auto fetch = [&](auto row_tag, Raw16& raw, int stage, bool checked) {
+    constexpr bool kRow = decltype(row_tag)::value;
+    const int64_t first = p.t0 + (int64_t)stage * kStage + ks * 16;
+    const __amdgpu_buffer_rsrc_t rs = stage_rsrc(chan, first, n);
+    const int valid = p.t_end - (int)first;
+    if (kRow) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        if (!checked) {
+          raw.w[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff_row, r * n, 0);
+        } else {
+          const bool ok = row_ok && r + 8 * half < valid;
+          const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_row : kOob, r * n, 0);
+          raw.w[r] = ok ? v : kZeroSamples;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        if (!checked) {
+          raw.w[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff_col, r * n, 0);
+        } else {
+          const bool ok = col_ok && r < valid;
+          const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_col : kOob, r * n, 0);
+          raw.w[r] = ok ? v : kZeroSamples;
+        }
+      }
+    }
+  };
+  auto stage_checked = [&](int stage) {
+    return !panels_full || p.t0 + (int64_t)stage * kStage + ks * 16 + 16 > p.t_end;
+  };
+
+  auto run = [&](auto row_tag, auto mfma_tag) {
+    constexpr bool kRow = decltype(row_tag)::value;
+    constexpr bool kMfma = decltype(mfma_tag)::value;
+    // staging slices, spread over the four MFMA steps of a stage
+    auto slice = [&](int seg, Raw16& dec, int buf, uint32_t* tx0, uint32_t* tx1) {
+      if (kRow) {
+        if (seg == 1) transpose_rows(dec.w, tx0, tx1);
+        if (seg == 2) decode_rows_half(tx0, tx1, 0, row_dst0 + buf * kBufBytes, 4 * l32);
+        if (seg == 3) decode_rows_half(tx0, tx1, 1, row_dst0 + buf * kBufBytes, 4 * l32);
+      } else {
+        uint8_t* dst = col_dst0 + buf * kBufBytes;
+        if (seg == 1) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) *reinterpret_cast<uint32_t*>(dst + r * kColRowStride) = dec.w[r];
+        }
+        if (seg == 2) {
+#pragma unroll
+          for (int r = 8; r < 16; ++r) *reinterpret_cast<uint32_t*>(dst + r * kColRowStride) = dec.w[r];
+        }
+      }
+    };
+    auto body = [&](auto fast_tag, int cur, Raw16& dec, Raw16& ld, int ld_stage, bool do_dec,
+                    bool do_ld) {
+      constexpr bool kFast = decltype(fast_tag)::value;
+      const uint8_t* base = lds + cur * kBufBytes;
+      Frags f0, f1;
+      uint32_t tx0[4], tx1[4];
+      __builtin_amdgcn_sched_barrier(0);
+      if (kMfma) load_frags(f0, base, 0);
+      if (kFast) fetch(row_tag, ld, ld_stage, false);
+      else if (do_ld) fetch(row_tag, ld, ld_stage, stage_checked(ld_stage));
+      __builtin_amdgcn_sched_barrier(0);
+      if (kMfma) load_frags(f1, base, 1);
+      if (kFast || do_dec) slice(1, dec, cur ^ 1, tx0, tx1);
+      if (kMfma) mfma_step(f0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (kMfma) load_frags(f0, base, 2);
+      if (kFast || do_dec) slice(2, dec, cur ^ 1, tx0, tx1);
+      if (kMfma) mfma_step(f1);
+      __builtin_amdgcn_sched_barrier(0);
+      if (kMfma) load_frags(f1, base, 3);
+      if (kFast || do_dec) slice(3, dec, cur ^ 1, tx0, tx1);
+      if (kMfma) mfma_step(f0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (kMfma) mfma_step(f1);
+      __builtin_amdgcn_sched_barrier(0);
+      __syncthreads();
+    };
+
+    Raw16 ra, rb_;
+    fetch(row_tag, ra, stage_begin, stage_checked(stage_begin));
+    if (stage_begin + 1 < stage_end)
+      fetch(row_tag, rb_, stage_begin + 1, stage_checked(stage_begin + 1));
+    {
+      uint32_t tx0[4], tx1[4];
+      slice(1, ra, 0, tx0, tx1);
+      slice(2, ra, 0, tx0, tx1);
+      slice(3, ra, 0, tx0, tx1);
+    }
+    __syncthreads();
+    const int full_stages = panels_full ? (p.t_end - p.t0) / kStage : 0;
+    const int fast_end = min(stage_end, full_stages);
+    int s = stage_begin;
+    for (; s + 3 < fast_end; s += 2) {
+      body(std::true_type{}, 0, rb_, ra, s + 2, true, true);
+      body(std::true_type{}, 1, ra, rb_, s + 3, true, true);
+    }
+    for (; s < stage_end; ++s) {
+      const bool do_dec = s + 1 < stage_end, do_ld = s + 2 < stage_end;
+      if (((s - stage_begin) & 1) == 0)
+        body(std::false_type{}, 0, rb_, ra, s + 2, do_dec, do_ld);
+      else
+        body(std::false_type{}, 1, ra, rb_, s + 2, do_dec, do_ld);
+    }
+  };
+  if (row_role) {
+    if (wave_active) run(std::true_type{}, std::true_type{});
+    else run(std::true_type{}, std::false_type{});
+  } else {
+    if (wave_active) run(std::false_type{}, std::true_type{});
+    else run(std::false_type{}, std::false_type{});
+  }
+
+  if (!wave_active) return;
+  const int64_t n64 = n;
+  const int64_t entries = n64 * (n64 + 1) / 2;
+  int32_t* out = p.vis + (int64_t)ch * entries * 2;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int j = col0 + wc * 64 + cb * 32 + l32;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = row0 + wr * 64 + rb * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        if (i <= j && j < n) {
+          int32_t* o = out + 2 * tri_index(n64, i, j);
+          const int re = acc_re[rb][cb][r] >> 4, im = acc_im[rb][cb][r] >> 4;
+          if (p.atomic_out) {
+            atomicAdd(o, re);
+            atomicAdd(o + 1, im);
+          } else if (p.accumulate) {
+            const v2i old = *reinterpret_cast<const v2i*>(o);
+            *reinterpret_cast<v2i*>(o) = v2i{old.x + re, old.y + im};
+          } else {
+            *reinterpret_cast<v2i*>(o) = v2i{re, im};
+          }
+        }
+      }
+    }
+}
+
 }  // namespace
 
 int64_t wide_tiles_per_channel(int n) {
@@ -388,7 +678,7 @@ int64_t wide_tiles_per_channel(int n) {
 int64_t wide_max_samples_per_launch() { return kMaxSamplesPerLaunch; }
 
 hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
-                       int accumulate, int split, hipStream_t stream) {
+                       int accumulate, int split, int waves, hipStream_t stream) {
   if (t_count <= 0 || t_count > kMaxSamplesPerLaunch || t0 < 0 || t0 + t_count > t)
     return hipErrorInvalidValue;
   WideParams p;
@@ -412,7 +702,10 @@ hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int
   p.full_panels = (n % kCols) == 0;
   const int64_t grid = (int64_t)p.ntiles * f * split;
   if (grid <= 0 || grid > 0x7fffffff) return hipErrorInvalidConfiguration;
-  xcorr_wide_kernel<<<dim3((unsigned)grid), dim3(kThreads), 0, stream>>>(p);
+  if (waves == 8)
+    xcorr_wide8_kernel<<<dim3((unsigned)grid), dim3(kThreads8), 0, stream>>>(p);
+  else
+    xcorr_wide_kernel<<<dim3((unsigned)grid), dim3(kThreads), 0, stream>>>(p);
   return hipGetLastError();
 }
 

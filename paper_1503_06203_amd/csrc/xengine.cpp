@@ -38,10 +38,12 @@ struct Variant {
 // Index = variant id.
 const Variant kVariants[] = {
     {"tile128_kc64_mfma32x32x32"},        // any n, any input alignment
-    {"wide128x256_kc64_mfma32x32x32"},    // n % 4 == 0, 4-byte aligned input
+    {"wide128x256_w4_kc64_mfma32x32x32"}, // n % 4 == 0, 4-byte aligned input
+    {"wide128x256_w8_kc64_mfma32x32x32"}, // n % 4 == 0, 4-byte aligned input
 };
 constexpr int kVariantTile128 = 0;
 constexpr int kVariantWide = 1;
+constexpr int kVariantWide8 = 2;
 constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
 
 bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
@@ -122,25 +124,27 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
   }
   int split = split_t > 0 ? split_t : 1;
   const bool aligned = (n % 4 == 0) && ((uintptr_t)d_in % 4 == 0);
-  if (variant == -1) variant = aligned ? kVariantWide : kVariantTile128;
-  if (variant == kVariantWide && !aligned)
+  if (variant == -1) variant = aligned ? kVariantWide8 : kVariantTile128;
+  const bool wide = variant == kVariantWide || variant == kVariantWide8;
+  if (wide && !aligned)
     return fail(XENG_EINVAL, "variant %s needs n %% 4 == 0 and a 4-byte aligned input",
                 kVariants[variant].name);
-  if (variant == kVariantWide && (int64_t)n * 32 >= ((int64_t)1 << 31))
+  if (wide && (int64_t)n * 32 >= ((int64_t)1 << 31))
     return fail(XENG_EINVAL, "variant %s supports n < 2^26", kVariants[variant].name);
   if (split > 1 && !accumulate) {
     hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
     if (e != hipSuccess) return device_fail(e, "zero fill");
   }
   hipError_t e = hipSuccess;
-  if (variant == kVariantWide) {
+  if (wide) {
     // one launch per window of at most wide_max_samples_per_launch() samples;
     // windows after the first add to what the earlier ones wrote
     const int64_t win = xeng::wide_max_samples_per_launch();
     for (int64_t t0 = 0; t0 < t && e == hipSuccess; t0 += win) {
       const int cnt = (int)std::min<int64_t>(win, t - t0);
       const int acc = (t0 == 0) ? accumulate : 1;
-      e = xeng::launch_wide(d_in, d_vis, n, f, t, (int)t0, cnt, acc, split, stream);
+      e = xeng::launch_wide(d_in, d_vis, n, f, t, (int)t0, cnt, acc, split,
+                            variant == kVariantWide8 ? 8 : 4, stream);
     }
   } else {
     e = xeng::launch_tile128(d_in, d_vis, n, f, t, accumulate, split, aligned, stream);

@@ -145,19 +145,20 @@ VARIANT_SHAPES = [(1, 64, 4), (2, 97, 128), (1, 200, 256), (2, 333, 260), (1, 10
                   (1, 130, 512), (3, 64, 132), (1, 4097, 256), (2, 1, 1024)]
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("f,t,n", VARIANT_SHAPES)
 def test_each_variant_matches_oracle(variant, f, t, n):
     x = synth.quantized_gaussian(f, t, n, 3.0, seed=f * 7919 + t * 31 + n)
     full_check(x, variant=variant, split=1)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("split", [2, 5])
-def test_wide_variant_time_split(split):
+def test_wide_variant_time_split(variant, split):
     x = synth.quantized_gaussian(1, 1500, 512, 2.5, seed=split + 40)
     xd = x.to(DEV)
     ref = gpu_correlate(xd, variant=0, split=1)
-    got = gpu_correlate(xd, variant=1, split=split)
+    got = gpu_correlate(xd, variant=variant, split=split)
     assert torch.equal(ref, got)
     assert_same(got, oracle.correlate(x.numpy()))
 
