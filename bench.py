@@ -149,12 +149,79 @@ def cpu_baseline(w, budget_s: float = 15.0):
                       % (k, w.f, n_elems, w.t, ops, dt)}
 
 
+def bench_batched(steps: int, warmup: int):
+    """64 mixed jobs: one persistent launch (plan) vs one plain launch per job,
+    and the plan replayed from a captured HIP graph."""
+    import torch
+
+    import paper_1503_06203_amd as xe
+    import synth
+    from paper_1503_06203_amd import metrics
+    from synth import workloads
+
+    specs = workloads.batched_jobs()
+    dev = "cuda:0"
+    jobs = [(synth.quantized_gaussian(s["f"], s["t"], s["n"], s["sigma"], s["seed"], device=dev),
+             xe.new_vis(s["n"], s["f"], device=dev)) for s in specs]
+    ops = sum(metrics.effective_ops(s["n"], s["f"], s["t"]) for s in specs)
+    plan = xe.Plan(jobs)
+    tuned_ms = plan.autotune(reps=2)
+    wall_p, per_p = time_steps(plan.run, steps, warmup)
+    plain_vis = [xe.new_vis(s["n"], s["f"], device=dev) for s in specs]
+
+    def per_job():
+        for (x, _), v in zip(jobs, plain_vis):
+            xe.correlate(x, v)
+
+    wall_j, per_j = time_steps(per_job, max(1, steps // 2), 1)
+    same = all(bool(torch.equal(v, pv)) for (_, v), pv in zip(jobs, plain_vis))
+    plan.capture_graph()
+    wall_g, per_g = time_steps(plan.replay, steps, warmup)
+    del jobs, plain_vis
+    torch.cuda.empty_cache()
+    return {
+        "workload": "batched", "jobs": len(specs), "effective_ops": ops,
+        "plan_tops": round(ops / (sum(per_p) / len(per_p)) / 1e12, 2),
+        "graph_tops": round(ops / (sum(per_g) / len(per_g)) / 1e12, 2),
+        "per_job_launch_tops": round(ops / (sum(per_j) / len(per_j)) / 1e12, 2),
+        "speedup_vs_per_job": round((sum(per_j) / len(per_j)) / (sum(per_p) / len(per_p)), 3),
+        "bit_identical_to_per_job": same, "split": plan.split, "tiles": plan.items,
+        "autotune_best_ms": round(tuned_ms, 3),
+    }
+
+
+def bench_served(rate_hz: float = 2000.0, frames: int = 300):
+    """Poisson stream of frames through the continuous-batching server."""
+    import torch
+
+    import synth
+    from paper_1503_06203_amd import serve
+    from synth import workloads
+
+    arrivals, ns, fs, t = workloads.served_stream(rate_hz=rate_hz, frames=frames)
+    gen_seed = [0]
+
+    def frames_for(n, f):
+        gen_seed[0] += 1
+        return [synth.quantized_gaussian(f, t, n, 2.5, seed=5000 + gen_seed[0] * 10 + k,
+                                         device="cuda:0") for k in range(2)]
+
+    stats, acc = serve.run_stream(arrivals, ns, fs, t, frames_for, hbm_budget=200 << 30,
+                                  max_inflight=2)
+    del acc
+    torch.cuda.empty_cache()
+    stats["workload"] = "served"
+    stats["rate_hz"] = rate_hz
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="pathfinder", choices=["tiny", "pathfinder", "large_n"])
+    ap.add_argument("--workload", default="pathfinder",
+                    choices=["tiny", "pathfinder", "large_n", "batched", "served"])
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -168,6 +235,11 @@ def main():
         print("bench.py needs an MI355X GPU", file=sys.stderr)
         sys.exit(2)
     from synth import workloads
+
+    if args.workload in ("batched", "served"):
+        r = bench_batched(args.steps, args.warmup) if args.workload == "batched" else bench_served()
+        print(json.dumps(r), flush=True)
+        return
 
     w = workloads.WORKLOADS[args.workload]
     r = bench_workload(w, args.steps, args.warmup)
@@ -197,7 +269,7 @@ def main():
             "unit": "TOP/s",
             "frac": round(r["kernel_tops"] / PEAK_INT8_TOPS, 4),
             "traffic": traffic,
-            "kernel": "xcorr_tile128_kernel",
+            "kernel": "xcorr_wide8_kernel",
             "kernel_ms": round(r["kernel_ms"], 5),
             "algorithmic_ops_per_launch": r["ops_per_step"],
             "input_gbs": round(r["input_bytes"] / (r["kernel_ms"] / 1e3) / 1e9, 1),
@@ -212,6 +284,8 @@ def main():
                              "unit": "TOPS", "ms_per_step": round(s["ms_per_step"], 4),
                              "kernel_tops": round(s["kernel_tops"], 3),
                              "frac_int8_peak": round(s["kernel_tops"] / PEAK_INT8_TOPS, 4)}
+        line["batched"] = bench_batched(10, 2)
+        line["served"] = bench_served()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

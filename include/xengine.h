@@ -100,6 +100,98 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
                                    int64_t t_prev, int accumulate, int variant, int split_t,
                                    void* hip_stream);
 
+/* ---- Batched mode: many jobs in one persistent launch ------------------------
+ * A plan holds a list of independent correlation jobs (each as for
+ * xeng_correlate) of mixed n, f and t and runs them all with one launch of a
+ * persistent kernel that pulls tiles (channel, 128x256 tile, range of time
+ * stages) from a queue in device memory. Results are bit-identical to one
+ * xeng_correlate per job. Jobs need n % 4 == 0 and 4-byte aligned inputs; the
+ * outputs of different jobs must not overlap.
+ *
+ * The plan's device image (job table, tile queue, counters) lives in a
+ * workspace of xeng_plan_workspace_bytes() bytes that the caller allocates and
+ * passes in; the library keeps no device memory. Order of calls:
+ *   xeng_plan_create -> xeng_plan_upload (copies the image, stream-ordered)
+ *   -> xeng_plan_run (kernel launches only; may be captured in a graph)
+ *   -> per new frame: xeng_plan_set_frame (rewrites the job table) -> run.
+ * A run leaves its counters reset, so runs can follow each other or be
+ * replayed from a graph without re-uploading. Runs on one workspace must not
+ * overlap in time.
+ */
+typedef struct xeng_plan xeng_plan;
+typedef struct xeng_job {
+  const uint8_t* d_in;   /* device uint8_t[f][t][n] */
+  int32_t* d_vis;        /* device int32_t[f][n(n+1)/2][2] */
+  int n, f, t;
+  int64_t t_prev;        /* samples already summed in d_vis (0 unless accumulating) */
+  int accumulate;        /* 0 overwrite, 1 add */
+} xeng_job;
+
+/* Build a plan (host only). tune_cache_path (may be NULL) names a text file
+ * written by xeng_plan_autotune; a tuned time split for the same job shapes is
+ * applied. */
+xeng_status xeng_plan_create(xeng_plan** out, const xeng_job* jobs, int njobs,
+                             const char* tune_cache_path);
+size_t xeng_plan_workspace_bytes(const xeng_plan* plan);
+int64_t xeng_plan_items(const xeng_plan* plan);   /* tiles in the queue; -1 if plan is NULL */
+int xeng_plan_split(const xeng_plan* plan);       /* stages are split this many ways per tile */
+xeng_status xeng_plan_upload(xeng_plan* plan, void* d_workspace, void* hip_stream);
+/* Rebind every job to a new frame: d_in[k] (NULL keeps the inputs) and
+ * accumulate (1: add to the sums, subject to the int32 range guard). */
+xeng_status xeng_plan_set_frame(xeng_plan* plan, const uint8_t* const* d_in, int accumulate,
+                                void* d_workspace, void* hip_stream);
+xeng_status xeng_plan_run(xeng_plan* plan, void* d_workspace, void* hip_stream);
+/* Capture one run into a HIP graph owned by the plan (uses a private stream),
+ * and replay it on hip_stream. The graph reads the workspace captured with it. */
+xeng_status xeng_plan_graph_capture(xeng_plan* plan, void* d_workspace);
+xeng_status xeng_plan_graph_launch(xeng_plan* plan, void* hip_stream);
+/* Time the plan with several time splits per tile (running it reps times
+ * each, writing the jobs' outputs), keep the fastest, re-upload, and append the
+ * choice to tune_cache_path (may be NULL). best_ms may be NULL. */
+xeng_status xeng_plan_autotune(xeng_plan* plan, void* d_workspace, void* hip_stream, int reps,
+                               const char* tune_cache_path, float* best_ms);
+void xeng_plan_destroy(xeng_plan* plan);
+
+/* ---- Serving mode: continuous batching of streamed frames --------------------
+ * A server accepts correlation frames as they arrive. Each job (one stream of
+ * frames of one (n, f) shape) owns a device accumulator int32[f][n(n+1)/2][2]
+ * that its frames add into; the job's first frame overwrites it. A call of
+ * xeng_server_step() retires finished work and then launches, on each free
+ * slot, one persistent-kernel step holding the oldest pending frame of every
+ * job that has no frame in flight; frames that arrive meanwhile join later
+ * steps, and up to max_inflight steps run concurrently on the device (each on
+ * a stream of its own, ordered after the work queued so far on hip_stream, the
+ * stream the frames are produced on). Results are bit-identical to
+ * xeng_correlate over each job's frames in order.
+ *
+ * Admission by memory: xeng_job_open refuses (XENG_EBUSY) an accumulator that
+ * would push the open accumulators past hbm_budget bytes; a frame is launched
+ * only while accumulators plus frames in flight stay within hbm_budget, and
+ * otherwise waits. The workspace (ws_bytes of caller device memory, split in
+ * max_inflight slots) holds the per-step tile queues. Served jobs need
+ * n % 4 == 0; frames need 4-byte aligned input and 1 <= t <= 1 048 512.
+ * Frame buffers must stay valid until their ticket is done. Latency is
+ * measured from xeng_submit to the device-side completion of the frame's step.
+ */
+typedef struct xeng_server xeng_server;
+xeng_status xeng_server_create(xeng_server** out, size_t hbm_budget, int max_inflight,
+                               void* d_workspace, size_t ws_bytes, void* hip_stream);
+xeng_status xeng_job_open(xeng_server* srv, int n, int f, int32_t* d_vis, int64_t* job_id);
+xeng_status xeng_submit(xeng_server* srv, int64_t job_id, const uint8_t* d_frame, int t,
+                        uint64_t* ticket);
+/* launched (may be NULL) receives the number of frames started by this call. */
+xeng_status xeng_server_step(xeng_server* srv, int* launched);
+/* done = 1 once the frame's sums are in the accumulator; latency_us is then
+ * the submit-to-completion time (else -1). */
+xeng_status xeng_poll(xeng_server* srv, uint64_t ticket, int* done, double* latency_us);
+/* Run until every submitted frame is done (blocks). */
+xeng_status xeng_server_drain(xeng_server* srv);
+/* XENG_EBUSY while the job has frames queued or in flight. */
+xeng_status xeng_job_close(xeng_server* srv, int64_t job_id);
+xeng_status xeng_server_stats(xeng_server* srv, int64_t* open_jobs, int64_t* pending_frames,
+                              int64_t* inflight_steps, size_t* bytes_in_use);
+void xeng_server_destroy(xeng_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,15 @@ from . import metrics
 from ._lib import XengError, check, lib
 
 __all__ = ["correlate", "correlate_variant", "new_vis", "vis_entries", "tri_index",
-           "tile_count", "variants", "XengError", "metrics", "MAX_SAMPLES"]
+           "tile_count", "variants", "XengError", "metrics", "MAX_SAMPLES", "Plan", "Server"]
+
+
+def __getattr__(name):
+    # batched / serving wrappers, imported on first use
+    if name in ("Plan", "Server"):
+        from . import batch
+        return getattr(batch, name)
+    raise AttributeError(name)
 
 MAX_SAMPLES = metrics.MAX_SAMPLES
 

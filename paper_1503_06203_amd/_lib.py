@@ -28,6 +28,20 @@ c_i64 = ctypes.c_int64
 c_int = ctypes.c_int
 c_vp = ctypes.c_void_p
 c_cp = ctypes.c_char_p
+c_size = ctypes.c_size_t
+c_u64 = ctypes.c_uint64
+c_f32p = ctypes.POINTER(ctypes.c_float)
+c_intp = ctypes.POINTER(ctypes.c_int)
+c_i64p = ctypes.POINTER(ctypes.c_int64)
+c_u64p = ctypes.POINTER(ctypes.c_uint64)
+c_dblp = ctypes.POINTER(ctypes.c_double)
+c_sizep = ctypes.POINTER(ctypes.c_size_t)
+
+
+class XengJob(ctypes.Structure):
+    """Mirror of struct xeng_job."""
+    _fields_ = [("d_in", c_vp), ("d_vis", c_vp), ("n", c_int), ("f", c_int), ("t", c_int),
+                ("t_prev", c_i64), ("accumulate", c_int)]
 
 # name -> (restype, argtypes); one line per symbol declared in include/xengine.h
 SIGNATURES = {
@@ -41,6 +55,26 @@ SIGNATURES = {
     "xeng_variant_name": (c_cp, [c_int]),
     "xeng_correlate_variant": (c_int, [c_vp, c_vp, c_int, c_int, c_int, c_i64, c_int, c_int,
                                        c_int, c_vp]),
+    "xeng_plan_create": (c_int, [ctypes.POINTER(c_vp), ctypes.POINTER(XengJob), c_int, c_cp]),
+    "xeng_plan_workspace_bytes": (c_size, [c_vp]),
+    "xeng_plan_items": (c_i64, [c_vp]),
+    "xeng_plan_split": (c_int, [c_vp]),
+    "xeng_plan_upload": (c_int, [c_vp, c_vp, c_vp]),
+    "xeng_plan_set_frame": (c_int, [c_vp, ctypes.POINTER(c_vp), c_int, c_vp, c_vp]),
+    "xeng_plan_run": (c_int, [c_vp, c_vp, c_vp]),
+    "xeng_plan_graph_capture": (c_int, [c_vp, c_vp]),
+    "xeng_plan_graph_launch": (c_int, [c_vp, c_vp]),
+    "xeng_plan_autotune": (c_int, [c_vp, c_vp, c_vp, c_int, c_cp, c_f32p]),
+    "xeng_plan_destroy": (None, [c_vp]),
+    "xeng_server_create": (c_int, [ctypes.POINTER(c_vp), c_size, c_int, c_vp, c_size, c_vp]),
+    "xeng_job_open": (c_int, [c_vp, c_int, c_int, c_vp, c_i64p]),
+    "xeng_submit": (c_int, [c_vp, c_i64, c_vp, c_int, c_u64p]),
+    "xeng_server_step": (c_int, [c_vp, c_intp]),
+    "xeng_poll": (c_int, [c_vp, c_u64, c_intp, c_dblp]),
+    "xeng_server_drain": (c_int, [c_vp]),
+    "xeng_job_close": (c_int, [c_vp, c_i64]),
+    "xeng_server_stats": (c_int, [c_vp, c_i64p, c_i64p, c_i64p, c_sizep]),
+    "xeng_server_destroy": (None, [c_vp]),
 }
 
 

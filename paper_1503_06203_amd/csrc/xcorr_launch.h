@@ -28,4 +28,39 @@ hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int
 int64_t wide_max_samples_per_launch();
 int64_t wide_tiles_per_channel(int n);
 
+// ---- batched mode: one persistent launch over a queue of tiles --------------
+// Device-side images written by the host plan into the caller's workspace.
+struct QueueJob {            // one correlation job (one launch window of it)
+  const uint8_t* in;
+  int32_t* vis;
+  int n, f, t;               // elements, channels, samples per channel
+  int t0, t_end;             // window of samples this job sums
+  int nbr, ntiles, total_stages;
+  int accumulate, atomic_out, full_panels;
+  int zero_first;            // zero vis before the queue runs (atomic sums, not accumulating)
+};
+struct QueueItem {           // one tile of one channel over a range of stages
+  int job, ch, tile, stage_begin, stage_end, pad[3];
+};
+constexpr int kQueueParts = 8;   // one sub-queue per XCD
+struct QueueHeader {
+  unsigned cursor[kQueueParts];  // next item of each sub-queue (self-resetting)
+  unsigned done;                 // workgroups that have finished (self-resetting)
+  int part_begin[kQueueParts + 1];  // items of sub-queue k: [part_begin[k], part_begin[k+1])
+  int jobs_offset;               // byte offset of the QueueJob array
+  int items_offset;              // byte offset of the QueueItem array
+  int pad[5];
+};
+// Byte offsets of the job and item arrays in a queue workspace.
+__host__ __device__ inline size_t queue_jobs_offset() {
+  return (sizeof(QueueHeader) + 255) / 256 * 256;
+}
+__host__ __device__ inline size_t queue_items_offset(int njobs) {
+  return (queue_jobs_offset() + sizeof(QueueJob) * (size_t)njobs + 255) / 256 * 256;
+}
+// Launch the persistent kernel over a queue workspace prepared by the host.
+hipError_t launch_queue(void* d_ws, int grid, hipStream_t stream);
+int queue_stage_samples();
+int64_t queue_tiles_per_channel(int n);
+
 }  // namespace xeng

@@ -153,6 +153,21 @@ __device__ inline uint32_t neg_s8(uint32_t x) {
   return ((x ^ 0x7F7F7F7Fu) + 0x01010101u) ^ 0x80808080u;
 }
 
+// Tile t of a channel -> (row block bi of 128, column block bj of 256). Tiles
+// are ordered column block by column block; column block J holds the row
+// blocks I <= 2J+1, the ones that reach the upper triangle.
+__device__ inline void tile_coords(int tile, int nbr, int* bi_out, int* bj_out) {
+  int bj = 0, bi = tile;
+  while (true) {
+    const int cnt = min(2 * bj + 2, nbr);
+    if (bi < cnt) break;
+    bi -= cnt;
+    ++bj;
+  }
+  *bi_out = bi;
+  *bj_out = bj;
+}
+
 __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
 
@@ -415,30 +430,11 @@ struct Raw16 {
   uint32_t w[16];
 };
 
-__global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
-  // With two waves per SIMD each wave has 256 registers. An AGPR operand here
-  // tells the compiler the kernel uses accumulation registers, so it splits
-  // them 128 VGPR + 128 AGPR and keeps the 128 accumulators out of the VGPRs.
-  asm volatile("; accumulators live in AGPRs" ::"a"(0));
-
-  const int logical = xcd_logical_id(blockIdx.x, gridDim.x);
-  const int tile = logical % p.ntiles;
-  const int rest = logical / p.ntiles;
-  const int split_idx = rest % p.split;
-  const int ch = rest / p.split;
-  int bj = 0, bi = tile;
-  while (true) {
-    const int cnt = min(2 * bj + 2, p.nbr);
-    if (bi < cnt) break;
-    bi -= cnt;
-    ++bj;
-  }
+// One tile of one channel over stages [stage_begin, stage_end) of the launch
+// window in p. Shared by the per-tile kernel and the persistent queue kernel.
+__device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, int ch, int bi,
+                                           int bj, int stage_begin, int stage_end) {
   const int row0 = bi * kRows, col0 = bj * kCols;
-  const int stage_begin = split_idx * p.stages_per_split;
-  const int stage_end = min(stage_begin + p.stages_per_split, p.total_stages);
-  if (stage_begin >= stage_end) return;
-
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int half = lane >> 5, l32 = lane & 31;
@@ -665,6 +661,95 @@ __global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p)
       }
     }
 }
+__global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
+  // With two waves per SIMD each wave has 256 registers. An AGPR operand here
+  // tells the compiler the kernel uses accumulation registers, so it splits
+  // them 128 VGPR + 128 AGPR and keeps the 128 accumulators out of the VGPRs.
+  asm volatile("; accumulators live in AGPRs" ::"a"(0));
+  const int logical = xcd_logical_id(blockIdx.x, gridDim.x);
+  const int tile = logical % p.ntiles;
+  const int rest = logical / p.ntiles;
+  const int split_idx = rest % p.split;
+  const int ch = rest / p.split;
+  int bi, bj;
+  tile_coords(tile, p.nbr, &bi, &bj);
+  const int stage_begin = split_idx * p.stages_per_split;
+  const int stage_end = min(stage_begin + p.stages_per_split, p.total_stages);
+  if (stage_begin >= stage_end) return;
+  wide8_tile(p, lds, ch, bi, bj, stage_begin, stage_end);
+}
+
+
+// Persistent workgroups over a queue of tiles of many jobs (batched mode).
+// Workgroup w serves sub-queue w % 8 (the XCD it runs on, so neighbouring
+// tiles of a channel share that XCD's L2) and then steals from the others.
+// Every workgroup leaves once all sub-queues are empty; the last one out
+// resets the counters, so the workspace is ready for the next launch (no
+// memset, which keeps the launch capturable in a graph).
+__global__ __launch_bounds__(kThreads8, 1) void xcorr_queue_kernel(uint8_t* ws) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
+  __shared__ int next_item;
+  asm volatile("; accumulators live in AGPRs" ::"a"(0));
+  QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws);
+  const QueueJob* jobs = reinterpret_cast<const QueueJob*>(ws + hdr->jobs_offset);
+  const QueueItem* items = reinterpret_cast<const QueueItem*>(ws + hdr->items_offset);
+  int part = blockIdx.x % kQueueParts, tried = 0;
+  while (true) {
+    if (threadIdx.x == 0) {
+      int it = -1;
+      while (tried < kQueueParts) {
+        const int b = hdr->part_begin[part], e = hdr->part_begin[part + 1];
+        if (b < e) {
+          const unsigned k = atomicAdd(&hdr->cursor[part], 1u);
+          if ((int)k < e - b) {
+            it = b + (int)k;
+            break;
+          }
+        }
+        part = (part + 1) % kQueueParts;
+        ++tried;
+      }
+      next_item = it;
+    }
+    __syncthreads();
+    const int it = next_item;
+    __syncthreads();
+    if (it < 0) break;
+    const QueueItem q = items[it];
+    const QueueJob& J = jobs[q.job];
+    WideParams p;
+    p.in = J.in;
+    p.vis = J.vis;
+    p.n = J.n;
+    p.f = J.f;
+    p.t = J.t;
+    p.t0 = J.t0;
+    p.t_end = J.t_end;
+    p.nbr = J.nbr;
+    p.nbc = 0;
+    p.ntiles = J.ntiles;
+    p.split = 1;
+    p.stages_per_split = J.total_stages;
+    p.total_stages = J.total_stages;
+    p.accumulate = J.accumulate;
+    p.atomic_out = J.atomic_out;
+    p.full_panels = J.full_panels;
+    int bi, bj;
+    tile_coords(q.tile, p.nbr, &bi, &bj);
+    wide8_tile(p, lds, q.ch, bi, bj, q.stage_begin, q.stage_end);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned d = atomicAdd(&hdr->done, 1u);
+    if (d == gridDim.x - 1) {
+      for (int k = 0; k < kQueueParts; ++k) hdr->cursor[k] = 0u;
+      hdr->done = 0u;
+      __threadfence();
+    }
+  }
+}
 
 }  // namespace
 
@@ -676,6 +761,16 @@ int64_t wide_tiles_per_channel(int n) {
 }
 
 int64_t wide_max_samples_per_launch() { return kMaxSamplesPerLaunch; }
+
+int queue_stage_samples() { return kStage; }
+int64_t queue_tiles_per_channel(int n) { return wide_tiles_per_channel(n); }
+
+hipError_t launch_queue(void* d_ws, int grid, hipStream_t stream) {
+  if (grid <= 0) return hipErrorInvalidConfiguration;
+  xcorr_queue_kernel<<<dim3((unsigned)grid), dim3(kThreads8), 0, stream>>>(
+      reinterpret_cast<uint8_t*>(d_ws));
+  return hipGetLastError();
+}
 
 hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
                        int accumulate, int split, int waves, hipStream_t stream) {

@@ -11,12 +11,14 @@
 #include <string>
 
 #include "xcorr_launch.h"
+#include "xengine_internal.h"
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-xeng_status fail(xeng_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+namespace xeng {
+
 xeng_status fail(xeng_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -27,9 +29,16 @@ xeng_status fail(xeng_status st, const char* fmt, ...) {
   return st;
 }
 
-xeng_status device_fail(hipError_t err, const char* what) {
+xeng_status device_error(hipError_t err, const char* what) {
   return fail(XENG_EDEVICE, "%s: %s", what, hipGetErrorString(err));
 }
+
+}  // namespace xeng
+
+namespace {
+using xeng::check_job;
+using xeng::device_error;
+using xeng::fail;
 
 struct Variant {
   const char* name;
@@ -51,6 +60,9 @@ bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
   return na && nb && a0 < b0 + nb && b0 < a0 + na;
 }
 
+}  // namespace
+
+namespace xeng {
 // Shared validation of one correlation job; fills byte counts on success.
 xeng_status check_job(const uint8_t* d_in, const int32_t* d_vis, int n, int f, int t,
                       int64_t t_prev, int accumulate, size_t* in_bytes, size_t* vis_bytes) {
@@ -78,8 +90,7 @@ xeng_status check_job(const uint8_t* d_in, const int32_t* d_vis, int n, int f, i
     return fail(XENG_EINVAL, "d_in and d_vis overlap");
   return XENG_OK;
 }
-
-}  // namespace
+}  // namespace xeng
 
 extern "C" {
 
@@ -120,7 +131,7 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
   if (t == 0) {
     if (accumulate) return XENG_OK;
     hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
-    return e == hipSuccess ? XENG_OK : device_fail(e, "zero fill");
+    return e == hipSuccess ? XENG_OK : device_error(e, "zero fill");
   }
   int split = split_t > 0 ? split_t : 1;
   const bool aligned = (n % 4 == 0) && ((uintptr_t)d_in % 4 == 0);
@@ -133,7 +144,7 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
     return fail(XENG_EINVAL, "variant %s supports n < 2^26", kVariants[variant].name);
   if (split > 1 && !accumulate) {
     hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
-    if (e != hipSuccess) return device_fail(e, "zero fill");
+    if (e != hipSuccess) return device_error(e, "zero fill");
   }
   hipError_t e = hipSuccess;
   if (wide) {
@@ -149,7 +160,7 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
   } else {
     e = xeng::launch_tile128(d_in, d_vis, n, f, t, accumulate, split, aligned, stream);
   }
-  if (e != hipSuccess) return device_fail(e, "correlation kernel launch");
+  if (e != hipSuccess) return device_error(e, "correlation kernel launch");
   return XENG_OK;
 }
 

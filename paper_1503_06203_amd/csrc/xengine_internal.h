@@ -1,0 +1,21 @@
+// xengine_internal.h -- error reporting and argument checks shared by the
+// C ABI translation units (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "xengine.h"
+
+namespace xeng {
+
+// Record a message for xeng_last_error() and return st.
+xeng_status fail(xeng_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+// XENG_EDEVICE with the HIP error string.
+xeng_status device_error(hipError_t err, const char* what);
+// Validate one correlation job; fills its input and output byte counts.
+xeng_status check_job(const uint8_t* d_in, const int32_t* d_vis, int n, int f, int t,
+                      int64_t t_prev, int accumulate, size_t* in_bytes, size_t* vis_bytes);
+
+}  // namespace xeng

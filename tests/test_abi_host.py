@@ -100,3 +100,24 @@ def test_python_binding_errors_without_gpu():
     v = torch.zeros((1, 10, 2), dtype=torch.int32)
     with pytest.raises(TypeError):
         xe.correlate(x, v)            # CPU tensors: there is no CPU path
+
+
+def test_plan_host_logic(lib):
+    """Plan building is host-only: item counts, workspace size, validation."""
+    from paper_1503_06203_amd._lib import XengJob
+    import ctypes
+    jobs = (XengJob * 3)()
+    base_in, base_vis = 0x100000000, 0x900000000
+    shapes = [(256, 2, 1000), (64, 1, 64), (2048, 1, 100)]
+    for k, (n, f, t) in enumerate(shapes):
+        jobs[k] = XengJob(base_in + k * (1 << 28), base_vis + k * (1 << 28), n, f, t, 0, 0)
+    h = ctypes.c_void_p()
+    assert lib.xeng_plan_create(ctypes.byref(h), jobs, 3, None) == 0
+    # 128x256 tiles reaching the upper triangle: N=256 -> 2, N=64 -> 1, N=2048 -> 72
+    assert lib.xeng_plan_items(h) == 2 * 2 + 1 * 1 + 72 * 1
+    assert lib.xeng_plan_split(h) == 1
+    assert lib.xeng_plan_workspace_bytes(h) > 0
+    lib.xeng_plan_destroy(h)
+    jobs[1] = XengJob(base_in, base_vis, 6, 1, 10, 0, 0)        # n % 4 != 0
+    assert lib.xeng_plan_create(ctypes.byref(h), jobs, 3, None) == EINVAL
+    assert b"n % 4" in lib.xeng_last_error()
