@@ -224,6 +224,9 @@ def main():
                     choices=["tiny", "pathfinder", "large_n", "batched", "served"])
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="also copy 1 GiB device to device (a transfer of known size that "
+                         "scales the FETCH_SIZE / WRITE_SIZE hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (frequency "
@@ -243,6 +246,12 @@ def main():
 
     w = workloads.WORKLOADS[args.workload]
     r = bench_workload(w, args.steps, args.warmup)
+    if args.copy_reference:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     digest = kernel_source_digest()
     traffic = recorded_traffic(w.name, digest)
     line = {

@@ -132,6 +132,8 @@ typedef struct xeng_job {
  * applied. */
 xeng_status xeng_plan_create(xeng_plan** out, const xeng_job* jobs, int njobs,
                              const char* tune_cache_path);
+/* Workspace bytes for the plan; enough for every time split the autotuner may
+ * choose, so one allocation serves the plan for its whole life. */
 size_t xeng_plan_workspace_bytes(const xeng_plan* plan);
 int64_t xeng_plan_items(const xeng_plan* plan);   /* tiles in the queue; -1 if plan is NULL */
 int xeng_plan_split(const xeng_plan* plan);       /* stages are split this many ways per tile */

@@ -43,6 +43,8 @@ __global__ void queue_fill_kernel(const uint8_t* ws) {
     out[k] = make_int2(0, 0);
 }
 
+constexpr int kMaxSplit = 8;   // largest per-tile time split the autotuner tries
+
 int device_cu_count() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
@@ -68,6 +70,7 @@ struct xeng_plan {
   std::vector<xeng::QueueItem> items;
   std::vector<uint8_t> image;      // header + job table + items, as uploaded
   int split = 1;                   // stage split per item (autotuned)
+  size_t ws_bytes = 0;             // workspace for the largest split the tuner tries
   int grid = 0;
   bool needs_fill = false;
   hipGraph_t graph = nullptr;
@@ -240,9 +243,16 @@ xeng_status xeng_plan_create(xeng_plan** out, const xeng_job* jobs, int njobs,
     while (std::getline(in, line)) {
       std::istringstream ls(line);
       int split = 0;
-      if (ls >> key >> split && key == want && split >= 1 && split <= 64) pl->split = split;
+      if (ls >> key >> split && key == want && split >= 1 && split <= kMaxSplit)
+        pl->split = split;
     }
   }
+  // size the workspace for the largest split the autotuner may choose
+  const int chosen = pl->split;
+  pl->split = kMaxSplit;
+  build_items(pl);
+  pl->ws_bytes = pl->image.size();
+  pl->split = chosen;
   build_items(pl);
   write_jobs(pl);
   *out = pl;
@@ -250,7 +260,7 @@ xeng_status xeng_plan_create(xeng_plan** out, const xeng_job* jobs, int njobs,
 }
 
 size_t xeng_plan_workspace_bytes(const xeng_plan* plan) {
-  return plan == nullptr ? 0 : plan->image.size();
+  return plan == nullptr ? 0 : plan->ws_bytes;
 }
 
 int64_t xeng_plan_items(const xeng_plan* plan) {
@@ -345,7 +355,7 @@ xeng_status xeng_plan_autotune(xeng_plan* plan, void* d_workspace, void* hip_str
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (reps < 1) reps = 1;
   drop_graph(plan);
-  const int candidates[] = {1, 2, 3, 4, 6, 8};
+  const int candidates[] = {1, 2, 3, 4, 6, kMaxSplit};
   int best = plan->split;
   float best_t = -1.f;
   hipEvent_t e0 = nullptr, e1 = nullptr;
