@@ -32,6 +32,25 @@ PEAK_INT8_TOPS = 5000.0      # MI355X dense int8 MFMA, TOP/s
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
 
 
+# kernel symbol of each library variant (the name rocprofv3 reports)
+KERNEL_OF_VARIANT = {
+    "tile128": "xcorr_tile128_kernel",
+    "wide128x256_w4": "xcorr_wide_kernel",
+    "wide128x256_w8": "xcorr_wide8_kernel",
+    "tri256": "xcorr_tri_kernel",
+}
+
+
+def dispatched_kernel(n: int, f: int, t: int):
+    """(kernel symbol, variant name, time split) the library runs for this shape."""
+    import paper_1503_06203_amd as xe
+    _, split, name = xe.choose_variant(n, f, t)
+    for prefix, kern in KERNEL_OF_VARIANT.items():
+        if name.startswith(prefix):
+            return kern, name, split
+    return name, name, split
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_1503_06203_amd", "csrc", "*"))):
@@ -254,6 +273,7 @@ def main():
         del src, dst
     digest = kernel_source_digest()
     traffic = recorded_traffic(w.name, digest)
+    kern, vname, vsplit = dispatched_kernel(w.n, w.f, w.t)
     line = {
         "metric": "effective correlation TOPS (8 ops/complex MAC) + % int8 MFMA peak",
         "value": round(r["value"], 3),
@@ -278,7 +298,9 @@ def main():
             "unit": "TOP/s",
             "frac": round(r["kernel_tops"] / PEAK_INT8_TOPS, 4),
             "traffic": traffic,
-            "kernel": "xcorr_wide8_kernel",
+            "kernel": kern,
+            "variant": vname,
+            "time_split": vsplit,
             "kernel_ms": round(r["kernel_ms"], 5),
             "algorithmic_ops_per_launch": r["ops_per_step"],
             "input_gbs": round(r["input_bytes"] / (r["kernel_ms"] / 1e3) / 1e9, 1),

@@ -100,6 +100,17 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
                                    int64_t t_prev, int accumulate, int variant, int split_t,
                                    void* hip_stream);
 
+/*
+ * The variant and time split xeng_correlate would use for a job of this shape
+ * (host only, no device work). input_aligned: the input pointer is 4-byte
+ * aligned. Kernels: tri256 (n <= 256, n % 4 == 0, aligned input: one workgroup
+ * per channel covers the whole triangle), wide128x256_w8 (other aligned n % 4
+ * == 0 jobs), tile128 (everything else). Returns XENG_EINVAL for n < 1, f < 1
+ * or t < 0, or a NULL output pointer.
+ */
+xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* variant,
+                                int* split_t);
+
 /* ---- Batched mode: many jobs in one persistent launch ------------------------
  * A plan holds a list of independent correlation jobs (each as for
  * xeng_correlate) of mixed n, f and t and runs them all with one launch of a

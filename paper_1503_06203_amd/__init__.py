@@ -14,7 +14,7 @@ from __future__ import annotations
 from . import metrics
 from ._lib import XengError, check, lib
 
-__all__ = ["correlate", "correlate_variant", "new_vis", "vis_entries", "tri_index",
+__all__ = ["correlate", "correlate_variant", "choose_variant", "new_vis", "vis_entries", "tri_index",
            "tile_count", "variants", "XengError", "metrics", "MAX_SAMPLES", "Plan", "Server"]
 
 
@@ -72,6 +72,16 @@ def correlate_variant(x, vis, variant: int, split_t: int = 1, t_prev: int = 0,
                                        int(t_prev), int(bool(accumulate)), int(variant),
                                        int(split_t), _stream_ptr(stream)))
     return vis
+
+
+def choose_variant(n: int, f: int, t: int, aligned: bool = True):
+    """(variant id, time split, variant name) that correlate() uses for a job
+    of this shape; aligned = the input pointer is 4-byte aligned."""
+    import ctypes
+    v, sp = ctypes.c_int(), ctypes.c_int()
+    check(lib().xeng_choose_variant(int(n), int(f), int(t), int(bool(aligned)), ctypes.byref(v),
+                                    ctypes.byref(sp)))
+    return v.value, sp.value, variants()[v.value]
 
 
 def new_vis(n: int, f: int, device="cuda"):

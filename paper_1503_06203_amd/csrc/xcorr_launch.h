@@ -28,6 +28,17 @@ hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int
 int64_t wide_max_samples_per_launch();
 int64_t wide_tiles_per_channel(int n);
 
+// Triangle kernel for n <= tri_max_elements() (n % 4 == 0, 4-byte aligned
+// input): one workgroup per channel (times split) computes the channel's whole
+// upper triangle. Sums samples [t0, t0 + t_count) of each channel; sums are
+// unscaled, so one launch may cover any t_count. split > 1 divides the time
+// axis and combines with int32 atomic adds (the caller zero-fills vis first
+// when not accumulating).
+hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
+                      int accumulate, int split, hipStream_t stream);
+int tri_max_elements();
+int tri_stage_samples();
+
 // ---- batched mode: one persistent launch over a queue of tiles --------------
 // Device-side images written by the host plan into the caller's workspace.
 struct QueueJob {            // one correlation job (one launch window of it)

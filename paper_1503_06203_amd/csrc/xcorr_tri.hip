@@ -1,0 +1,386 @@
+// xcorr_tri.hip -- gfx950 correlation kernel for arrays of at most 256
+// elements: one workgroup computes the whole upper triangle of a channel.
+//
+// Same contraction as the other kernels (paper Sec. II-A, Eq. 1 and 2):
+//   Re V_ij = P_i . P_j,  Im V_ij = Q_i . P_j,   P_e = [Re e, Im e],
+//   Q_e = [Im e, -Re e]  over the time axis,
+// on v_mfma_i32_32x32x32_i8, over the triangle of 32x32 blocks that Sec. II-C
+// and Fig. 1 draw (36 blocks for 256 elements). Shape, chosen for gfx950:
+//   * 8 waves, two per SIMD. SIMD s owns block rows s and 7-s: (8-s) + (s+1)
+//     = 9 blocks, so the four SIMDs carry equal MFMA work. The SIMD's first
+//     wave takes row s, columns s..s+4; its second wave the other four blocks.
+//   * every operand, row or column, is decoded once per workgroup into LDS
+//     slabs P = [Re g, Re g+1, Im g, Im g+1] and N = [-Re g, -Re g+1] (each
+//     dword = 4 consecutive samples of one component). Q is the upper half of
+//     P followed by N, so the MFMA loop itself does no decode work.
+//   * packed bytes go from HBM straight into LDS (buffer_load ... lds), two
+//     stages ahead of use. Each wave loads 8 sample rows per stage and is the
+//     only reader of them: it waits for its own loads only, and the stage
+//     barrier never waits for memory.
+//   * a wave decodes its 8 samples with ds_read_b64_tr_b8, whose 8x8 byte
+//     transpose hands each lane 8 consecutive samples of one element.
+//
+// Blocks of the triangle that lie past n (n < 256) are computed from padding
+// and never stored; entries below the diagonal of a diagonal block likewise
+// (Sec. II-C computes and ignores them).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "xcorr_device.h"
+#include "xcorr_launch.h"
+
+namespace xeng {
+
+namespace {
+
+constexpr int kThreads = 512;                   // 8 waves, two per SIMD
+constexpr int kElems = 256;                     // elements one workgroup covers
+constexpr int kStage = 64;                      // samples per stage
+constexpr int kRawStride = kElems + 32;         // LDS bytes per raw sample row (bank spread)
+constexpr int kRawBytes = kStage * kRawStride;  // 18 KiB per raw buffer
+constexpr int kPBuf = kElems * 16;              // P slabs of one 8-sample group, one buffer
+constexpr int kNBuf = kElems * 8;               // N slabs of one group, one buffer
+constexpr int kPGroup = 2 * kPBuf;              // a group's slabs in both buffers
+constexpr int kNGroup = 2 * kNBuf;
+constexpr int kGroups = kStage / 8;             // 8-sample groups per stage (= waves)
+constexpr uint32_t kOob = 0x80000000u;          // buffer offset past every record: load returns 0
+
+struct TriParams {
+  const uint8_t* in;
+  int32_t* vis;
+  int n, f;
+  int t;                 // samples per channel (channel stride is t * n bytes)
+  int t0, t_end;         // this launch sums samples [t0, t_end)
+  int split;             // workgroups along time per channel
+  int stages_per_split;
+  int total_stages;
+  int full_stages;       // stages whose 64 samples all lie before t_end
+  int accumulate;
+  int atomic_out;
+};
+
+// ---- block programs ---------------------------------------------------------------
+// A wave's share of the 8x8 block triangle, relative to its base block (the
+// SIMD index for the first wave of a SIMD, 0 for the second):
+//   p[]  blocks whose P slabs the wave reads each MFMA step (A and B sides)
+//   nq[] blocks whose N slabs it reads (the rows it multiplies as A)
+//   slot k computes block (p[sa[k]], p[sb[k]]) with N slabs nq[sn[k]].
+struct ProgA {  // row s, columns s..s+4
+  static constexpr int kNP = 5, kNN = 1, kNS = 5;
+  static constexpr int p[kNP] = {0, 1, 2, 3, 4};
+  static constexpr int nq[kNN] = {0};
+  static constexpr int sa[kNS] = {0, 0, 0, 0, 0};
+  static constexpr int sn[kNS] = {0, 0, 0, 0, 0};
+  static constexpr int sb[kNS] = {0, 1, 2, 3, 4};
+};
+template <int S>
+struct ProgB;
+template <>
+struct ProgB<0> {  // (0,5) (0,6) (0,7) (7,7)
+  static constexpr int kNP = 4, kNN = 2, kNS = 4;
+  static constexpr int p[kNP] = {0, 5, 6, 7};
+  static constexpr int nq[kNN] = {0, 7};
+  static constexpr int sa[kNS] = {0, 0, 0, 3};
+  static constexpr int sn[kNS] = {0, 0, 0, 1};
+  static constexpr int sb[kNS] = {1, 2, 3, 3};
+};
+template <>
+struct ProgB<1> {  // (1,6) (1,7) (6,6) (6,7)
+  static constexpr int kNP = 3, kNN = 2, kNS = 4;
+  static constexpr int p[kNP] = {1, 6, 7};
+  static constexpr int nq[kNN] = {1, 6};
+  static constexpr int sa[kNS] = {0, 0, 1, 1};
+  static constexpr int sn[kNS] = {0, 0, 1, 1};
+  static constexpr int sb[kNS] = {1, 2, 1, 2};
+};
+template <>
+struct ProgB<2> {  // (2,7) (5,5) (5,6) (5,7)
+  static constexpr int kNP = 4, kNN = 2, kNS = 4;
+  static constexpr int p[kNP] = {2, 5, 6, 7};
+  static constexpr int nq[kNN] = {2, 5};
+  static constexpr int sa[kNS] = {0, 1, 1, 1};
+  static constexpr int sn[kNS] = {0, 1, 1, 1};
+  static constexpr int sb[kNS] = {3, 1, 2, 3};
+};
+template <>
+struct ProgB<3> {  // (4,4) (4,5) (4,6) (4,7)
+  static constexpr int kNP = 4, kNN = 1, kNS = 4;
+  static constexpr int p[kNP] = {4, 5, 6, 7};
+  static constexpr int nq[kNN] = {4};
+  static constexpr int sa[kNS] = {0, 0, 0, 0};
+  static constexpr int sn[kNS] = {0, 0, 0, 0};
+  static constexpr int sb[kNS] = {0, 1, 2, 3};
+};
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+typedef __attribute__((address_space(3))) v2i* lds_v2i_ptr;
+
+// Stage barrier for LDS traffic only: this wave's LDS reads and writes are
+// complete, then all waves meet. Loads still in flight into the raw buffers
+// are not waited for (each wave waits for its own before reading them).
+__device__ inline void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt left at their maximum
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Wait until at most kLeft of this wave's vector-memory operations are in
+// flight. They complete in issue order, so issuing a stage's 8 loads and then
+// waiting for kLeft = 8 means every earlier load has landed in LDS. The
+// compiler's own tracking of loads into LDS is not relied on: it does not
+// carry across loop back-edges. The empty asm statements keep memory
+// operations from moving across the wait.
+template <int kLeft>
+__device__ inline void vm_wait() {
+  static_assert(kLeft >= 0 && kLeft < 16, "vmcnt field");
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | kLeft);  // vmcnt(kLeft); lgkmcnt, expcnt at maximum
+  asm volatile("" ::: "memory");
+}
+
+// Keep the first `valid` bytes (samples) of w, turn the rest into zero samples.
+__device__ inline uint32_t keep_samples(uint32_t w, int valid) {
+  const uint32_t m = valid >= 4 ? 0xFFFFFFFFu : (valid <= 0 ? 0u : (1u << (8 * valid)) - 1u);
+  return (w & m) | (kZeroSamples & ~m);
+}
+
+template <class Prog>
+__device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, int sb, int se,
+                                        uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
+                                        uint8_t* dec_n) {
+  constexpr int kNP = Prog::kNP, kNN = Prog::kNN, kNS = Prog::kNS;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int half = lane >> 5, l32 = lane & 31;
+  const int n = p.n;
+  const uint8_t* chan = p.in + (int64_t)ch * p.t * (int64_t)n;
+
+  // ---- loads: this wave fetches sample rows 8*wave .. 8*wave+7 of a stage; a
+  // lane carries four elements, and lanes past n fetch nothing.
+  const uint32_t voff = (4 * lane < n) ? 4u * (uint32_t)lane : kOob;
+  auto fetch = [&](uint8_t* raw, int st, bool checked) {
+    // a sample index (< 2^24) that is uniform across the wave; saying so keeps
+    // the buffer descriptor in scalar registers
+    const int64_t first = __builtin_amdgcn_readfirstlane(p.t0 + st * kStage + 8 * wave);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t*>(chan + first * n), 0, 0x7fffffff, 0x00020000);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (checked && first + r >= p.t_end) break;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rs, (lds_void_ptr)(raw + (8 * wave + r) * kRawStride), 4, voff, r * n, 0, 0);
+    }
+  };
+
+  // ---- decode: ds_read_b64_tr_b8 over the wave's 8 rows. In each 16-lane
+  // group the even lanes name the rows of elements e0..e0+7 and the odd lanes
+  // those of e0+8..e0+15; lane k of the group receives element e0+k, byte m =
+  // sample m. Read i covers elements 64*i .. 64*i+63 (lane = element - 64*i).
+  const int lq = lane & 15;
+  const int tr_off = (8 * wave + (lq >> 1)) * kRawStride + 16 * ((lane >> 4) & 3) + 8 * (lq & 1);
+  uint8_t* const wr_p = dec_p + wave * kPGroup + lane * 16;
+  uint8_t* const wr_n = dec_n + wave * kNGroup + lane * 8;
+  auto decode = [&](const uint8_t* raw, int buf, int i, bool checked, int valid) {
+    const v2i w = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i_ptr)(raw + tr_off + 64 * i));
+    uint32_t a = (uint32_t)w.x, b = (uint32_t)w.y;
+    if (checked) {
+      a = keep_samples(a, valid);
+      b = keep_samples(b, valid - 4);
+    }
+    const uint32_t ha = fields_hi(a), hb = fields_hi(b);
+    const v4i ps = {(int)fields_to_s8(ha), (int)fields_to_s8(hb), (int)fields_to_s8(fields_lo(a)),
+                    (int)fields_to_s8(fields_lo(b))};
+    const v2i ns = {(int)fields_to_neg_s8(ha), (int)fields_to_neg_s8(hb)};
+    *reinterpret_cast<v4i*>(wr_p + buf * kPBuf + i * 1024) = ps;
+    *reinterpret_cast<v2i*>(wr_n + buf * kNBuf + i * 512) = ns;
+  };
+
+  // ---- MFMA operands: lane half h reads group 2*ks + h, element 32*block + l32
+  const uint8_t* const rd_p = dec_p + half * kPGroup + (32 * base + l32) * 16;
+  const uint8_t* const rd_n = dec_n + half * kNGroup + (32 * base + l32) * 8;
+  v16i acc_re[kNS], acc_im[kNS];
+#pragma unroll
+  for (int s = 0; s < kNS; ++s) {
+    acc_re[s] = v16i{};
+    acc_im[s] = v16i{};
+  }
+  auto kstep = [&](int buf, int ks) {
+    v4i pf[kNP];
+    v2i nf[kNN];
+#pragma unroll
+    for (int k = 0; k < kNP; ++k)
+      pf[k] = *reinterpret_cast<const v4i*>(rd_p + ks * 2 * kPGroup + buf * kPBuf +
+                                            Prog::p[k] * 512);
+#pragma unroll
+    for (int k = 0; k < kNN; ++k)
+      nf[k] = *reinterpret_cast<const v2i*>(rd_n + ks * 2 * kNGroup + buf * kNBuf +
+                                            Prog::nq[k] * 256);
+#pragma unroll
+    for (int s = 0; s < kNS; ++s) {
+      const v4i a = pf[Prog::sa[s]];
+      const v2i ng = nf[Prog::sn[s]];
+      const v4i q = {a.z, a.w, ng.x, ng.y};
+      const v4i b = pf[Prog::sb[s]];
+      acc_re[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc_re[s], 0, 0, 0);
+      acc_im[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(q, b, acc_im[s], 0, 0, 0);
+    }
+  };
+
+  // samples of this wave's group of stage st that lie before t_end
+  auto group_valid = [&](int st) {
+    const int v = __builtin_amdgcn_readfirstlane(p.t_end - (p.t0 + st * kStage + 8 * wave));
+    return v < 0 ? 0 : (v > 8 ? 8 : v);
+  };
+
+  // One stage st: fetch st+2 into the raw buffer st's data came from, decode
+  // st+1 (fetched one stage earlier) into the other operand buffer, and run
+  // the MFMA steps of st. kPar = (st - sb) & 1 selects the static buffers.
+  // The decode runs in every stage, also past se: it then fills the operand
+  // buffer that no later stage reads, and keeps each stage one basic block.
+  auto body = [&](auto fast, auto par, int st) {
+    constexpr bool kFast = decltype(fast)::value;
+    constexpr int kPar = decltype(par)::value;
+    uint8_t* const raw_ld = kPar ? raw1 : raw0;
+    const uint8_t* const raw_dc = kPar ? raw0 : raw1;
+    if (kFast) {
+      fetch(raw_ld, st + 2, false);
+      vm_wait<8>();   // this wave's rows of stage st+1 are in LDS
+    } else {
+      if (st + 2 < se) fetch(raw_ld, st + 2, true);
+      vm_wait<0>();
+    }
+    const int valid = kFast ? 8 : group_valid(st + 1);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      decode(raw_dc, kPar ^ 1, ks, !kFast, valid);
+      kstep(kPar, ks);
+    }
+    lds_barrier();
+  };
+
+  // ---- prologue: fetch sb and sb+1, decode sb ------------------------------------
+  fetch(raw0, sb, true);
+  if (sb + 1 < se) fetch(raw1, sb + 1, true);
+  vm_wait<0>();
+  {
+    const int valid = group_valid(sb);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) decode(raw0, 0, i, true, valid);
+  }
+  lds_barrier();
+
+  // ---- steady stages (st+2 exists and every stage up to it is full), then the rest
+  int st = sb;
+  const int fast_end = min(se, p.full_stages) - 2;
+  for (; st + 1 < fast_end; st += 2) {
+    body(std::true_type{}, std::integral_constant<int, 0>{}, st);
+    body(std::true_type{}, std::integral_constant<int, 1>{}, st + 1);
+  }
+  for (; st < se; ++st) {
+    if (((st - sb) & 1) == 0)
+      body(std::false_type{}, std::integral_constant<int, 0>{}, st);
+    else
+      body(std::false_type{}, std::integral_constant<int, 1>{}, st);
+  }
+
+  // ---- epilogue: masked writes of i <= j < n into the packed triangle ------------
+  const int64_t n64 = n;
+  const int64_t entries = n64 * (n64 + 1) / 2;
+  int32_t* out = p.vis + (int64_t)ch * entries * 2;
+  auto store_all = [&](auto mode) {
+    constexpr int kMode = decltype(mode)::value;   // 0 store, 1 add, 2 atomic add
+#pragma unroll
+    for (int s = 0; s < kNS; ++s) {
+      const int rb = base + Prog::p[Prog::sa[s]], cb = base + Prog::p[Prog::sb[s]];
+      const int j = 32 * cb + l32;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = 32 * rb + 8 * (r >> 2) + 4 * half + (r & 3);
+        if (i <= j && j < n) {
+          int32_t* o = out + 2 * tri_index(n64, i, j);
+          const int re = acc_re[s][r], im = acc_im[s][r];
+          if (kMode == 2) {
+            atomicAdd(o, re);
+            atomicAdd(o + 1, im);
+          } else if (kMode == 1) {
+            const v2i old = *reinterpret_cast<const v2i*>(o);
+            *reinterpret_cast<v2i*>(o) = v2i{old.x + re, old.y + im};
+          } else {
+            *reinterpret_cast<v2i*>(o) = v2i{re, im};
+          }
+        }
+      }
+    }
+  };
+  if (p.atomic_out)
+    store_all(std::integral_constant<int, 2>{});
+  else if (p.accumulate)
+    store_all(std::integral_constant<int, 1>{});
+  else
+    store_all(std::integral_constant<int, 0>{});
+}
+
+__global__ __launch_bounds__(kThreads, 1) void xcorr_tri_kernel(TriParams p) {
+  // Each raw buffer is its own variable: the compiler then tracks the loads
+  // into one separately from reads of the other and waits only for those.
+  __shared__ __attribute__((aligned(16))) uint8_t raw0[kRawBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t raw1[kRawBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t dec_p[kGroups * kPGroup];  // 64 KiB
+  __shared__ __attribute__((aligned(16))) uint8_t dec_n[kGroups * kNGroup];  // 32 KiB
+  // Two waves per SIMD: 256 registers per wave. The accumulators (up to 160)
+  // stay in ordinary VGPRs; the compiler's default split when AGPRs are in
+  // use (128 + 128) could not hold them.
+  // grid x = channel, y = part of the time axis: no integer division, so
+  // every index below stays in scalar registers
+  const int ch = blockIdx.x, part = blockIdx.y;
+  const int sb = part * p.stages_per_split;
+  const int se = min(sb + p.stages_per_split, p.total_stages);
+  if (sb >= se) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int simd = wave & 3;
+  if (wave < 4) {
+    tri_run<ProgA>(p, ch, simd, sb, se, raw0, raw1, dec_p, dec_n);
+  } else {
+    switch (simd) {
+      case 0: tri_run<ProgB<0>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
+      case 1: tri_run<ProgB<1>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
+      case 2: tri_run<ProgB<2>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
+      default: tri_run<ProgB<3>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
+    }
+  }
+}
+
+}  // namespace
+
+int tri_max_elements() { return kElems; }
+int tri_stage_samples() { return kStage; }
+
+hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
+                      int accumulate, int split, hipStream_t stream) {
+  if (n < 1 || n > kElems || n % 4 != 0) return hipErrorInvalidValue;
+  if (t_count <= 0 || t0 < 0 || (int64_t)t0 + t_count > t) return hipErrorInvalidValue;
+  TriParams p;
+  p.in = in;
+  p.vis = vis;
+  p.n = n;
+  p.f = f;
+  p.t = t;
+  p.t0 = t0;
+  p.t_end = t0 + t_count;
+  p.total_stages = (t_count + kStage - 1) / kStage;
+  p.full_stages = t_count / kStage;
+  if (split < 1) split = 1;
+  if (split > p.total_stages) split = p.total_stages;
+  p.split = split;
+  p.stages_per_split = (p.total_stages + split - 1) / split;
+  p.accumulate = accumulate;
+  p.atomic_out = split > 1;
+  if (f <= 0 || split > 65535) return hipErrorInvalidConfiguration;
+  xcorr_tri_kernel<<<dim3((unsigned)f, (unsigned)split), dim3(kThreads), 0, stream>>>(p);
+  return hipGetLastError();
+}
+
+}  // namespace xeng

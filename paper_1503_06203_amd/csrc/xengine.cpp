@@ -33,6 +33,37 @@ xeng_status device_error(hipError_t err, const char* what) {
   return fail(XENG_EDEVICE, "%s: %s", what, hipGetErrorString(err));
 }
 
+int device_cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  return cus > 0 ? cus : 256;
+}
+
+int tri_auto_split(int f, int64_t t_count, int cus) {
+  // Cost model in stage times: rounds of workgroups x (stages per workgroup +
+  // a fixed cost for the prologue and the output writes, plus the atomic
+  // combine when split). A split keeps at least 16 stages per workgroup.
+  const int64_t stage = tri_stage_samples();
+  const int64_t stages = (t_count + stage - 1) / stage;
+  if (cus < 1) cus = 1;
+  int best = 1;
+  double best_cost = 0.0;
+  for (int split = 1; split <= 64; ++split) {
+    if (split > 1 && stages / split < 16) break;
+    const int64_t wgs = (int64_t)f * split;
+    const int64_t rounds = (wgs + cus - 1) / cus;
+    const double per_wg = (double)((stages + split - 1) / split) + (split > 1 ? 6.0 : 4.0);
+    const double cost = (double)rounds * per_wg;
+    if (split == 1 || cost < best_cost * 0.97) {
+      best = split;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 }  // namespace xeng
 
 namespace {
@@ -49,11 +80,21 @@ const Variant kVariants[] = {
     {"tile128_kc64_mfma32x32x32"},        // any n, any input alignment
     {"wide128x256_w4_kc64_mfma32x32x32"}, // n % 4 == 0, 4-byte aligned input
     {"wide128x256_w8_kc64_mfma32x32x32"}, // n % 4 == 0, 4-byte aligned input
+    {"tri256_w8_kc64_mfma32x32x32"},      // n <= 256, n % 4 == 0, 4-byte aligned input
 };
 constexpr int kVariantTile128 = 0;
 constexpr int kVariantWide = 1;
 constexpr int kVariantWide8 = 2;
+constexpr int kVariantTri = 3;
 constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// The kernel xeng_correlate uses: the triangle kernel where it applies (it
+// wastes the least MFMA work on small arrays), else the wide kernel for
+// dword-loadable inputs, else the general one.
+int default_variant(int n, bool aligned) {
+  if (aligned && n <= xeng::tri_max_elements()) return kVariantTri;
+  return aligned ? kVariantWide8 : kVariantTile128;
+}
 
 bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
   const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
@@ -133,21 +174,29 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
     hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
     return e == hipSuccess ? XENG_OK : device_error(e, "zero fill");
   }
-  int split = split_t > 0 ? split_t : 1;
   const bool aligned = (n % 4 == 0) && ((uintptr_t)d_in % 4 == 0);
-  if (variant == -1) variant = aligned ? kVariantWide8 : kVariantTile128;
+  const bool tri_ok = aligned && n <= xeng::tri_max_elements();
+  if (variant == -1) variant = default_variant(n, aligned);
   const bool wide = variant == kVariantWide || variant == kVariantWide8;
   if (wide && !aligned)
     return fail(XENG_EINVAL, "variant %s needs n %% 4 == 0 and a 4-byte aligned input",
                 kVariants[variant].name);
   if (wide && (int64_t)n * 32 >= ((int64_t)1 << 31))
     return fail(XENG_EINVAL, "variant %s supports n < 2^26", kVariants[variant].name);
+  if (variant == kVariantTri && !tri_ok)
+    return fail(XENG_EINVAL, "variant %s needs n <= %d, n %% 4 == 0 and a 4-byte aligned input",
+                kVariants[variant].name, xeng::tri_max_elements());
+  int split = split_t > 0 ? split_t : 1;
+  if (variant == kVariantTri && split_t == 0)
+    split = xeng::tri_auto_split(f, t, xeng::device_cu_count());
   if (split > 1 && !accumulate) {
     hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
     if (e != hipSuccess) return device_error(e, "zero fill");
   }
   hipError_t e = hipSuccess;
-  if (wide) {
+  if (variant == kVariantTri) {
+    e = xeng::launch_tri(d_in, d_vis, n, f, t, 0, t, accumulate, split, stream);
+  } else if (wide) {
     // one launch per window of at most wide_max_samples_per_launch() samples;
     // windows after the first add to what the earlier ones wrote
     const int64_t win = xeng::wide_max_samples_per_launch();
@@ -161,6 +210,18 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
     e = xeng::launch_tile128(d_in, d_vis, n, f, t, accumulate, split, aligned, stream);
   }
   if (e != hipSuccess) return device_error(e, "correlation kernel launch");
+  return XENG_OK;
+}
+
+xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* variant,
+                                int* split_t) {
+  if (n < 1 || f < 1 || t < 0)
+    return fail(XENG_EINVAL, "need n >= 1, f >= 1, t >= 0 (got n=%d f=%d t=%d)", n, f, t);
+  if (variant == nullptr || split_t == nullptr) return fail(XENG_EINVAL, "NULL output pointer");
+  const bool aligned = input_aligned != 0 && n % 4 == 0;
+  const int v = default_variant(n, aligned);
+  *variant = v;
+  *split_t = (v == kVariantTri && t > 0) ? xeng::tri_auto_split(f, t, xeng::device_cu_count()) : 1;
   return XENG_OK;
 }
 

@@ -17,5 +17,10 @@ xeng_status device_error(hipError_t err, const char* what);
 // Validate one correlation job; fills its input and output byte counts.
 xeng_status check_job(const uint8_t* d_in, const int32_t* d_vis, int n, int f, int t,
                       int64_t t_prev, int accumulate, size_t* in_bytes, size_t* vis_bytes);
+// Compute units of the current device (256 if the query fails).
+int device_cu_count();
+// Time split for the triangle kernel: f * split workgroups of one channel's
+// stages each, chosen to fill `cus` compute units in whole rounds.
+int tri_auto_split(int f, int64_t t_count, int cus);
 
 }  // namespace xeng

@@ -45,14 +45,6 @@ __global__ void queue_fill_kernel(const uint8_t* ws) {
 
 constexpr int kMaxSplit = 8;   // largest per-tile time split the autotuner tries
 
-int device_cu_count() {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 256;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 256;
-  return cus > 0 ? cus : 256;
-}
-
 }  // namespace
 
 struct PlanWindow {

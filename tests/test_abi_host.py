@@ -93,6 +93,24 @@ def test_unknown_variant(lib):
     assert lib.xeng_variant_name(0) is not None
 
 
+def test_choose_variant_dispatch_rule():
+    # triangle kernel for aligned n <= 256 with n % 4 == 0; wide kernel for other
+    # aligned n % 4 == 0; the general kernel otherwise
+    import paper_1503_06203_amd as xe
+    assert xe.choose_variant(256, 256, 16384)[2].startswith("tri256")
+    assert xe.choose_variant(4, 1, 10)[2].startswith("tri256")
+    assert xe.choose_variant(260, 4, 100)[2].startswith("wide128x256_w8")
+    assert xe.choose_variant(2048, 16, 65536)[2].startswith("wide128x256_w8")
+    assert xe.choose_variant(255, 4, 100)[2].startswith("tile128")
+    assert xe.choose_variant(256, 4, 100, aligned=False)[2].startswith("tile128")
+    # one channel of a long integration is split in time across workgroups
+    v, split, _ = xe.choose_variant(256, 1, 1 << 20)
+    assert split > 1
+    assert xe.choose_variant(256, 256, 16384)[1] == 1
+    with pytest.raises(xe.XengError):
+        xe.choose_variant(0, 1, 1)
+
+
 def test_python_binding_errors_without_gpu():
     import torch
     import paper_1503_06203_amd as xe
