@@ -39,8 +39,13 @@ hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int 
 int tri_max_elements();
 int tri_stage_samples();
 
-// ---- batched mode: one persistent launch over a queue of tiles --------------
-// Device-side images written by the host plan into the caller's workspace.
+// ---- batched mode: persistent launches over queues of work items --------------
+// Device-side images written by the host (plans, the server) into the caller's
+// workspace. Jobs with n <= tri_max_elements() run on the triangle kernel (one
+// item = one channel over a range of stages), the others on 128x256 tiles (one
+// item = one tile of one channel over a range of stages). Each kind has its own
+// queue header; both share one job table:
+//   [header, triangle items][header, tile items][job table][triangle items][tile items]
 struct QueueJob {            // one correlation job (one launch window of it)
   const uint8_t* in;
   int32_t* vis;
@@ -50,28 +55,77 @@ struct QueueJob {            // one correlation job (one launch window of it)
   int accumulate, atomic_out, full_panels;
   int zero_first;            // zero vis before the queue runs (atomic sums, not accumulating)
 };
-struct QueueItem {           // one tile of one channel over a range of stages
+struct QueueItem {           // one tile (or whole triangle) of one channel over a range of stages
   int job, ch, tile, stage_begin, stage_end, pad[3];
 };
 constexpr int kQueueParts = 8;   // one sub-queue per XCD
+constexpr int kQueueTri = 0, kQueueWide = 1, kQueueKinds = 2;
+constexpr int kQueueHeaderStride = 256;
 struct QueueHeader {
   unsigned cursor[kQueueParts];  // next item of each sub-queue (self-resetting)
   unsigned done;                 // workgroups that have finished (self-resetting)
   int part_begin[kQueueParts + 1];  // items of sub-queue k: [part_begin[k], part_begin[k+1])
   int jobs_offset;               // byte offset of the QueueJob array
-  int items_offset;              // byte offset of the QueueItem array
+  int items_offset;              // byte offset of this kind's QueueItem array
   int pad[5];
 };
-// Byte offsets of the job and item arrays in a queue workspace.
+static_assert(sizeof(QueueHeader) <= kQueueHeaderStride, "queue header size");
+// Byte offsets of the job table and of the first item array in a queue image.
 __host__ __device__ inline size_t queue_jobs_offset() {
-  return (sizeof(QueueHeader) + 255) / 256 * 256;
+  return (size_t)kQueueKinds * kQueueHeaderStride;
 }
 __host__ __device__ inline size_t queue_items_offset(int njobs) {
   return (queue_jobs_offset() + sizeof(QueueJob) * (size_t)njobs + 255) / 256 * 256;
 }
-// Launch the persistent kernel over a queue workspace prepared by the host.
-hipError_t launch_queue(void* d_ws, int grid, hipStream_t stream);
+// The header's offsets and item ranges, the item lists and the job table are
+// not written while a queue kernel runs (only cursor and done are, by atomics),
+// so kernels read them through the constant address space: scalar loads, whose
+// results stay in scalar registers and keep buffer descriptors scalar.
+typedef const __attribute__((address_space(4))) QueueHeader* QueueHeaderC;
+typedef const __attribute__((address_space(4))) QueueItem* QueueItemC;
+typedef const __attribute__((address_space(4))) QueueJob* QueueJobC;
+
+__device__ inline QueueItem load_item(QueueItemC items, int k) {
+  QueueItem q;
+  q.job = items[k].job;
+  q.ch = items[k].ch;
+  q.tile = items[k].tile;
+  q.stage_begin = items[k].stage_begin;
+  q.stage_end = items[k].stage_end;
+  return q;
+}
+__device__ inline QueueJob load_job(QueueJobC jobs, int k) {
+  QueueJob J;
+  J.in = jobs[k].in;
+  J.vis = jobs[k].vis;
+  J.n = jobs[k].n;
+  J.f = jobs[k].f;
+  J.t = jobs[k].t;
+  J.t0 = jobs[k].t0;
+  J.t_end = jobs[k].t_end;
+  J.nbr = jobs[k].nbr;
+  J.ntiles = jobs[k].ntiles;
+  J.total_stages = jobs[k].total_stages;
+  J.accumulate = jobs[k].accumulate;
+  J.atomic_out = jobs[k].atomic_out;
+  J.full_panels = jobs[k].full_panels;
+  J.zero_first = jobs[k].zero_first;
+  return J;
+}
+
 int queue_stage_samples();
 int64_t queue_tiles_per_channel(int n);
+int queue_kind_of(int n);
+// Build the image for job table `table` with `split` stage ranges per tile
+// (items[k] receives the item count of kind k). The job table must already
+// hold n, f, t0, t_end, total_stages and ntiles.
+void build_queue_image(const QueueJob* table, int njobs, int split, uint8_t** image_out,
+                       size_t* bytes_out, int64_t items[kQueueKinds]);
+// One persistent launch per kind with items, in order, on `stream`; grid =
+// workgroups (one per compute unit).
+hipError_t launch_queues(void* d_ws, const int64_t items[kQueueKinds], int grid,
+                         hipStream_t stream);
+hipError_t launch_queue_wide(void* d_ws, int header_offset, int grid, hipStream_t stream);
+hipError_t launch_queue_tri(void* d_ws, int header_offset, int grid, hipStream_t stream);
 
 }  // namespace xeng

@@ -56,7 +56,6 @@ struct TriParams {
   int split;             // workgroups along time per channel
   int stages_per_split;
   int total_stages;
-  int full_stages;       // stages whose 64 samples all lie before t_end
   int accumulate;
   int atomic_out;
 };
@@ -128,11 +127,11 @@ __device__ inline void lds_barrier() {
 }
 
 // Wait until at most kLeft of this wave's vector-memory operations are in
-// flight. They complete in issue order, so issuing a stage's 8 loads and then
-// waiting for kLeft = 8 means every earlier load has landed in LDS. The
-// compiler's own tracking of loads into LDS is not relied on: it does not
-// carry across loop back-edges. The empty asm statements keep memory
-// operations from moving across the wait.
+// flight. They retire in issue order, so issuing a stage's 8 loads and then
+// waiting for kLeft = 8 means every operation issued before them (the loads of
+// the previous stage among them) is complete. The compiler's own tracking of
+// loads into LDS is not relied on: it does not carry across loop back-edges.
+// The empty asm statements keep memory operations from moving across the wait.
 template <int kLeft>
 __device__ inline void vm_wait() {
   static_assert(kLeft >= 0 && kLeft < 16, "vmcnt field");
@@ -159,20 +158,24 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   const uint8_t* chan = p.in + (int64_t)ch * p.t * (int64_t)n;
 
   // ---- loads: this wave fetches sample rows 8*wave .. 8*wave+7 of a stage; a
-  // lane carries four elements, and lanes past n fetch nothing.
+  // lane carries four elements. Every stage issues exactly 8 loads per wave
+  // (the waits below count on it): the buffer descriptor's record count ends
+  // at t_end, so rows past it read nothing (their samples are masked in the
+  // decode), and lanes past n use an offset beyond every record.
   const uint32_t voff = (4 * lane < n) ? 4u * (uint32_t)lane : kOob;
-  auto fetch = [&](uint8_t* raw, int st, bool checked) {
-    // a sample index (< 2^24) that is uniform across the wave; saying so keeps
+  auto fetch = [&](uint8_t* raw, int st) {
+    // a sample index (< 2^25) that is uniform across the wave; saying so keeps
     // the buffer descriptor in scalar registers
-    const int64_t first = __builtin_amdgcn_readfirstlane(p.t0 + st * kStage + 8 * wave);
+    const int first = __builtin_amdgcn_readfirstlane(p.t0 + st * kStage + 8 * wave);
+    const int64_t bytes = (int64_t)(p.t_end - first) * n;
+    const int records = bytes <= 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : (int)bytes);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint8_t*>(chan + first * n), 0, 0x7fffffff, 0x00020000);
+        const_cast<uint8_t*>(chan + (int64_t)first * n), 0, records, 0x00020000);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      if (checked && first + r >= p.t_end) break;
+    for (int r = 0; r < 8; ++r)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rs, (lds_void_ptr)(raw + (8 * wave + r) * kRawStride), 4, voff, r * n, 0, 0);
-    }
+          rs, (lds_void_ptr)(raw + (8 * wave + r) * kRawStride), 4, voff + (uint32_t)(r * n), 0,
+          0, 0);
   };
 
   // ---- decode: ds_read_b64_tr_b8 over the wave's 8 rows. In each 16-lane
@@ -183,13 +186,12 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   const int tr_off = (8 * wave + (lq >> 1)) * kRawStride + 16 * ((lane >> 4) & 3) + 8 * (lq & 1);
   uint8_t* const wr_p = dec_p + wave * kPGroup + lane * 16;
   uint8_t* const wr_n = dec_n + wave * kNGroup + lane * 8;
-  auto decode = [&](const uint8_t* raw, int buf, int i, bool checked, int valid) {
-    const v2i w = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i_ptr)(raw + tr_off + 64 * i));
-    uint32_t a = (uint32_t)w.x, b = (uint32_t)w.y;
-    if (checked) {
-      a = keep_samples(a, valid);
-      b = keep_samples(b, valid - 4);
-    }
+  auto tr_read = [&](const uint8_t* raw, int i) {
+    return __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i_ptr)(raw + tr_off + 64 * i));
+  };
+  auto decode = [&](v2i w, int buf, int i, int valid) {
+    const uint32_t a = keep_samples((uint32_t)w.x, valid);
+    const uint32_t b = keep_samples((uint32_t)w.y, valid - 4);
     const uint32_t ha = fields_hi(a), hb = fields_hi(b);
     const v4i ps = {(int)fields_to_s8(ha), (int)fields_to_s8(hb), (int)fields_to_s8(fields_lo(a)),
                     (int)fields_to_s8(fields_lo(b))};
@@ -207,23 +209,28 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     acc_re[s] = v16i{};
     acc_im[s] = v16i{};
   }
-  auto kstep = [&](int buf, int ks) {
+  // Operand fragments of one 16-sample MFMA step.
+  struct Frags {
     v4i pf[kNP];
     v2i nf[kNN];
+  };
+  auto load_frags = [&](Frags& fr, int buf, int ks) {
 #pragma unroll
     for (int k = 0; k < kNP; ++k)
-      pf[k] = *reinterpret_cast<const v4i*>(rd_p + ks * 2 * kPGroup + buf * kPBuf +
-                                            Prog::p[k] * 512);
+      fr.pf[k] = *reinterpret_cast<const v4i*>(rd_p + ks * 2 * kPGroup + buf * kPBuf +
+                                               Prog::p[k] * 512);
 #pragma unroll
     for (int k = 0; k < kNN; ++k)
-      nf[k] = *reinterpret_cast<const v2i*>(rd_n + ks * 2 * kNGroup + buf * kNBuf +
-                                            Prog::nq[k] * 256);
+      fr.nf[k] = *reinterpret_cast<const v2i*>(rd_n + ks * 2 * kNGroup + buf * kNBuf +
+                                               Prog::nq[k] * 256);
+  };
+  auto mfma_step = [&](const Frags& fr) {
 #pragma unroll
     for (int s = 0; s < kNS; ++s) {
-      const v4i a = pf[Prog::sa[s]];
-      const v2i ng = nf[Prog::sn[s]];
+      const v4i a = fr.pf[Prog::sa[s]];
+      const v2i ng = fr.nf[Prog::sn[s]];
       const v4i q = {a.z, a.w, ng.x, ng.y};
-      const v4i b = pf[Prog::sb[s]];
+      const v4i b = fr.pf[Prog::sb[s]];
       acc_re[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc_re[s], 0, 0, 0);
       acc_im[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(q, b, acc_im[s], 0, 0, 0);
     }
@@ -235,56 +242,56 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     return v < 0 ? 0 : (v > 8 ? 8 : v);
   };
 
-  // One stage st: fetch st+2 into the raw buffer st's data came from, decode
-  // st+1 (fetched one stage earlier) into the other operand buffer, and run
-  // the MFMA steps of st. kPar = (st - sb) & 1 selects the static buffers.
-  // The decode runs in every stage, also past se: it then fills the operand
-  // buffer that no later stage reads, and keeps each stage one basic block.
-  auto body = [&](auto fast, auto par, int st) {
-    constexpr bool kFast = decltype(fast)::value;
+  // One stage st, software-pipelined: the step-0 fragments are requested
+  // first, then this wave's loads for st+2 and the transposing reads of its
+  // rows of st+1; each MFMA step then requests the next step's fragments and
+  // overlaps its MFMAs with the decode of one quarter of the elements of st+1
+  // (written to the other operand buffer). kPar = (st - sb) & 1 selects the
+  // static buffers. Stages past se are fetched and decoded as well (rows past
+  // t_end read nothing and decode to zero samples; within t_end they are
+  // simply not used): every stage is the same straight-line code.
+  auto body = [&](auto par, int st) {
     constexpr int kPar = decltype(par)::value;
     uint8_t* const raw_ld = kPar ? raw1 : raw0;
     const uint8_t* const raw_dc = kPar ? raw0 : raw1;
-    if (kFast) {
-      fetch(raw_ld, st + 2, false);
-      vm_wait<8>();   // this wave's rows of stage st+1 are in LDS
-    } else {
-      if (st + 2 < se) fetch(raw_ld, st + 2, true);
-      vm_wait<0>();
-    }
-    const int valid = kFast ? 8 : group_valid(st + 1);
+    Frags fr[2];
+    load_frags(fr[0], kPar, 0);
+    fetch(raw_ld, st + 2);
+    vm_wait<8>();   // all but the 8 loads just issued are done: rows of st+1 are in LDS
+    const int valid = group_valid(st + 1);
+    v2i rawv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rawv[i] = tr_read(raw_dc, i);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      decode(raw_dc, kPar ^ 1, ks, !kFast, valid);
-      kstep(kPar, ks);
+      if (ks < 3) load_frags(fr[(ks + 1) & 1], kPar, ks + 1);
+      decode(rawv[ks], kPar ^ 1, ks, valid);
+      mfma_step(fr[ks & 1]);
+      __builtin_amdgcn_sched_barrier(0);
     }
     lds_barrier();
   };
 
   // ---- prologue: fetch sb and sb+1, decode sb ------------------------------------
-  fetch(raw0, sb, true);
-  if (sb + 1 < se) fetch(raw1, sb + 1, true);
-  vm_wait<0>();
+  fetch(raw0, sb);
+  fetch(raw1, sb + 1);
+  vm_wait<8>();
   {
     const int valid = group_valid(sb);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) decode(raw0, 0, i, true, valid);
+    for (int i = 0; i < 4; ++i) decode(tr_read(raw0, i), 0, i, valid);
   }
   lds_barrier();
 
-  // ---- steady stages (st+2 exists and every stage up to it is full), then the rest
   int st = sb;
-  const int fast_end = min(se, p.full_stages) - 2;
-  for (; st + 1 < fast_end; st += 2) {
-    body(std::true_type{}, std::integral_constant<int, 0>{}, st);
-    body(std::true_type{}, std::integral_constant<int, 1>{}, st + 1);
+  for (; st + 1 < se; st += 2) {
+    body(std::integral_constant<int, 0>{}, st);
+    body(std::integral_constant<int, 1>{}, st + 1);
   }
-  for (; st < se; ++st) {
-    if (((st - sb) & 1) == 0)
-      body(std::false_type{}, std::integral_constant<int, 0>{}, st);
-    else
-      body(std::false_type{}, std::integral_constant<int, 1>{}, st);
-  }
+  if (st < se) body(std::integral_constant<int, 0>{}, st);
+  // loads issued for the two stages past se may still be writing LDS: let
+  // them land before the workgroup moves on (or ends and releases its LDS)
+  vm_wait<0>();
 
   // ---- epilogue: masked writes of i <= j < n into the packed triangle ------------
   const int64_t n64 = n;
@@ -323,6 +330,24 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     store_all(std::integral_constant<int, 0>{});
 }
 
+// The 8 waves of a workgroup each run their share of the triangle.
+__device__ __forceinline__ void tri_channel(const TriParams& p, int ch, int sb, int se,
+                                            uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
+                                            uint8_t* dec_n) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int simd = wave & 3;
+  if (wave < 4) {
+    tri_run<ProgA>(p, ch, simd, sb, se, raw0, raw1, dec_p, dec_n);
+  } else {
+    switch (simd) {
+      case 0: tri_run<ProgB<0>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
+      case 1: tri_run<ProgB<1>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
+      case 2: tri_run<ProgB<2>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
+      default: tri_run<ProgB<3>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_kernel(TriParams p) {
   // Each raw buffer is its own variable: the compiler then tracks the loads
   // into one separately from reads of the other and waits only for those.
@@ -339,16 +364,91 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_kernel(TriParams p) {
   const int sb = part * p.stages_per_split;
   const int se = min(sb + p.stages_per_split, p.total_stages);
   if (sb >= se) return;
+  tri_channel(p, ch, sb, se, raw0, raw1, dec_p, dec_n);
+}
+
+// Persistent workgroups over a queue of (job, channel, stage range) items of
+// many jobs (batched mode), with the sub-queue and stealing scheme of the
+// tile queue: workgroup w serves sub-queue w % 8 and then the others, and the
+// last workgroup out resets the counters for the next launch. Each wave picks
+// its block program once and runs the item loop with it (all waves meet at the
+// same barriers), so no program's set-up is live in another's loop.
+template <class Prog>
+__device__ __forceinline__ void tri_queue_loop(uint8_t* ws, int hdr_offset, int base,
+                                               uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
+                                               uint8_t* dec_n, int* next_item) {
+  QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws + hdr_offset);
+  const QueueHeaderC hdr_c = (QueueHeaderC)(ws + hdr_offset);
+  const QueueJobC jobs = (QueueJobC)(ws + hdr_c->jobs_offset);
+  const QueueItemC items = (QueueItemC)(ws + hdr_c->items_offset);
+  int part = blockIdx.x % kQueueParts, tried = 0;
+  while (true) {
+    if (threadIdx.x == 0) {
+      int it = -1;
+      while (tried < kQueueParts) {
+        const int b = hdr_c->part_begin[part], e = hdr_c->part_begin[part + 1];
+        if (b < e) {
+          const unsigned k = atomicAdd(&hdr->cursor[part], 1u);
+          if ((int)k < e - b) {
+            it = b + (int)k;
+            break;
+          }
+        }
+        part = (part + 1) % kQueueParts;
+        ++tried;
+      }
+      *next_item = it;
+    }
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(*next_item);
+    __syncthreads();
+    if (it < 0) break;
+    const QueueItem q = load_item(items, it);
+    const QueueJob J = load_job(jobs, q.job);
+    TriParams p;
+    p.in = J.in;
+    p.vis = J.vis;
+    p.n = J.n;
+    p.f = J.f;
+    p.t = J.t;
+    p.t0 = J.t0;
+    p.t_end = J.t_end;
+    p.split = 1;
+    p.stages_per_split = J.total_stages;
+    p.total_stages = J.total_stages;
+    p.accumulate = J.accumulate;
+    p.atomic_out = J.atomic_out;
+    tri_run<Prog>(p, q.ch, base, q.stage_begin, q.stage_end, raw0, raw1, dec_p, dec_n);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned d = atomicAdd(&hdr->done, 1u);
+    if (d == gridDim.x - 1) {
+      for (int k = 0; k < kQueueParts; ++k) hdr->cursor[k] = 0u;
+      hdr->done = 0u;
+      __threadfence();
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 1) void xcorr_tri_queue_kernel(uint8_t* ws,
+                                                                      int hdr_offset) {
+  __shared__ __attribute__((aligned(16))) uint8_t raw0[kRawBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t raw1[kRawBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t dec_p[kGroups * kPGroup];
+  __shared__ __attribute__((aligned(16))) uint8_t dec_n[kGroups * kNGroup];
+  __shared__ int next_item;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int simd = wave & 3;
   if (wave < 4) {
-    tri_run<ProgA>(p, ch, simd, sb, se, raw0, raw1, dec_p, dec_n);
+    tri_queue_loop<ProgA>(ws, hdr_offset, simd, raw0, raw1, dec_p, dec_n, &next_item);
   } else {
     switch (simd) {
-      case 0: tri_run<ProgB<0>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
-      case 1: tri_run<ProgB<1>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
-      case 2: tri_run<ProgB<2>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
-      default: tri_run<ProgB<3>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
+      case 0: tri_queue_loop<ProgB<0>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &next_item); break;
+      case 1: tri_queue_loop<ProgB<1>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &next_item); break;
+      case 2: tri_queue_loop<ProgB<2>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &next_item); break;
+      default: tri_queue_loop<ProgB<3>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &next_item); break;
     }
   }
 }
@@ -356,6 +456,13 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_kernel(TriParams p) {
 }  // namespace
 
 int tri_max_elements() { return kElems; }
+
+hipError_t launch_queue_tri(void* d_ws, int header_offset, int grid, hipStream_t stream) {
+  if (grid <= 0) return hipErrorInvalidConfiguration;
+  xcorr_tri_queue_kernel<<<dim3((unsigned)grid), dim3(kThreads), 0, stream>>>(
+      reinterpret_cast<uint8_t*>(d_ws), header_offset);
+  return hipGetLastError();
+}
 int tri_stage_samples() { return kStage; }
 
 hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
@@ -371,7 +478,6 @@ hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int 
   p.t0 = t0;
   p.t_end = t0 + t_count;
   p.total_stages = (t_count + kStage - 1) / kStage;
-  p.full_stages = t_count / kStage;
   if (split < 1) split = 1;
   if (split > p.total_stages) split = p.total_stages;
   p.split = split;

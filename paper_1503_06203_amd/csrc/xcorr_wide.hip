@@ -687,19 +687,20 @@ __global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p)
 // Every workgroup leaves once all sub-queues are empty; the last one out
 // resets the counters, so the workspace is ready for the next launch (no
 // memset, which keeps the launch capturable in a graph).
-__global__ __launch_bounds__(kThreads8, 1) void xcorr_queue_kernel(uint8_t* ws) {
+__global__ __launch_bounds__(kThreads8, 1) void xcorr_queue_kernel(uint8_t* ws, int hdr_offset) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
   __shared__ int next_item;
   asm volatile("; accumulators live in AGPRs" ::"a"(0));
-  QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws);
-  const QueueJob* jobs = reinterpret_cast<const QueueJob*>(ws + hdr->jobs_offset);
-  const QueueItem* items = reinterpret_cast<const QueueItem*>(ws + hdr->items_offset);
+  QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws + hdr_offset);
+  const QueueHeaderC hdr_c = (QueueHeaderC)(ws + hdr_offset);
+  const QueueJobC jobs = (QueueJobC)(ws + hdr_c->jobs_offset);
+  const QueueItemC items = (QueueItemC)(ws + hdr_c->items_offset);
   int part = blockIdx.x % kQueueParts, tried = 0;
   while (true) {
     if (threadIdx.x == 0) {
       int it = -1;
       while (tried < kQueueParts) {
-        const int b = hdr->part_begin[part], e = hdr->part_begin[part + 1];
+        const int b = hdr_c->part_begin[part], e = hdr_c->part_begin[part + 1];
         if (b < e) {
           const unsigned k = atomicAdd(&hdr->cursor[part], 1u);
           if ((int)k < e - b) {
@@ -713,11 +714,11 @@ __global__ __launch_bounds__(kThreads8, 1) void xcorr_queue_kernel(uint8_t* ws) 
       next_item = it;
     }
     __syncthreads();
-    const int it = next_item;
+    const int it = __builtin_amdgcn_readfirstlane(next_item);
     __syncthreads();
     if (it < 0) break;
-    const QueueItem q = items[it];
-    const QueueJob& J = jobs[q.job];
+    const QueueItem q = load_item(items, it);
+    const QueueJob J = load_job(jobs, q.job);
     WideParams p;
     p.in = J.in;
     p.vis = J.vis;
@@ -765,10 +766,10 @@ int64_t wide_max_samples_per_launch() { return kMaxSamplesPerLaunch; }
 int queue_stage_samples() { return kStage; }
 int64_t queue_tiles_per_channel(int n) { return wide_tiles_per_channel(n); }
 
-hipError_t launch_queue(void* d_ws, int grid, hipStream_t stream) {
+hipError_t launch_queue_wide(void* d_ws, int header_offset, int grid, hipStream_t stream) {
   if (grid <= 0) return hipErrorInvalidConfiguration;
   xcorr_queue_kernel<<<dim3((unsigned)grid), dim3(kThreads8), 0, stream>>>(
-      reinterpret_cast<uint8_t*>(d_ws));
+      reinterpret_cast<uint8_t*>(d_ws), header_offset);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -59,8 +60,8 @@ struct xeng_plan {
   std::vector<xeng_job> jobs;
   std::vector<int64_t> held;       // samples each job's sums hold after the configured frame
   std::vector<xeng::PlanWindow> windows;
-  std::vector<xeng::QueueItem> items;
-  std::vector<uint8_t> image;      // header + job table + items, as uploaded
+  int64_t items[xeng::kQueueKinds] = {0, 0};   // triangle items, tile items
+  std::vector<uint8_t> image;      // headers + job table + items, as uploaded
   int split = 1;                   // stage split per item (autotuned)
   size_t ws_bytes = 0;             // workspace for the largest split the tuner tries
   int grid = 0;
@@ -73,67 +74,10 @@ struct xeng_plan {
 namespace xeng {
 namespace {
 
-// Rebuild items, partition and device image for the current split.
-void build_items(xeng_plan* pl) {
+// The job table (one entry per window) for the plan's current jobs.
+std::vector<QueueJob> job_table(xeng_plan* pl) {
   const int stage = queue_stage_samples();
-  struct JobCost {
-    int w;
-    int64_t per_item;
-  };
-  std::vector<JobCost> order;
-  for (int w = 0; w < (int)pl->windows.size(); ++w) {
-    const auto& win = pl->windows[w];
-    const int stages = (win.t_end - win.t0 + stage - 1) / stage;
-    order.push_back({w, (stages + pl->split - 1) / pl->split});
-  }
-  std::stable_sort(order.begin(), order.end(),
-                   [](const JobCost& a, const JobCost& b) { return a.per_item > b.per_item; });
-  pl->items.clear();
-  std::vector<int64_t> cost;
-  for (const auto& jc : order) {
-    const auto& win = pl->windows[jc.w];
-    const xeng_job& job = pl->jobs[win.job];
-    const int stages = (win.t_end - win.t0 + stage - 1) / stage;
-    const int ntiles = (int)queue_tiles_per_channel(job.n);
-    const int per = (stages + pl->split - 1) / pl->split;
-    for (int ch = 0; ch < job.f; ++ch)
-      for (int tile = 0; tile < ntiles; ++tile)
-        for (int sb = 0; sb < stages; sb += per) {
-          QueueItem it{};
-          it.job = jc.w;
-          it.ch = ch;
-          it.tile = tile;
-          it.stage_begin = sb;
-          it.stage_end = std::min(stages, sb + per);
-          pl->items.push_back(it);
-          cost.push_back(it.stage_end - it.stage_begin);
-        }
-  }
-  // cut into kQueueParts contiguous parts of about equal total cost
-  const int64_t total = std::accumulate(cost.begin(), cost.end(), (int64_t)0);
-  QueueHeader hdr{};
-  int part = 0;
-  int64_t acc = 0;
-  hdr.part_begin[0] = 0;
-  for (size_t k = 0; k < cost.size() && part < kQueueParts - 1; ++k) {
-    acc += cost[k];
-    if (acc * kQueueParts >= total * (part + 1)) hdr.part_begin[++part] = (int)k + 1;
-  }
-  while (part < kQueueParts - 1) hdr.part_begin[++part] = (int)pl->items.size();
-  hdr.part_begin[kQueueParts] = (int)pl->items.size();
-  const int nw = (int)pl->windows.size();
-  hdr.jobs_offset = (int)queue_jobs_offset();
-  hdr.items_offset = (int)queue_items_offset(nw);
-  pl->image.assign(queue_items_offset(nw) + sizeof(QueueItem) * pl->items.size(), 0);
-  std::memcpy(pl->image.data(), &hdr, sizeof hdr);
-  std::memcpy(pl->image.data() + hdr.items_offset, pl->items.data(),
-              sizeof(QueueItem) * pl->items.size());
-}
-
-// Write the job table (inputs, flags) into the image.
-void write_jobs(xeng_plan* pl) {
-  const int stage = queue_stage_samples();
-  QueueJob* table = reinterpret_cast<QueueJob*>(pl->image.data() + queue_jobs_offset());
+  std::vector<QueueJob> table;
   pl->needs_fill = false;
   for (size_t w = 0; w < pl->windows.size(); ++w) {
     const auto& win = pl->windows[w];
@@ -156,8 +100,28 @@ void write_jobs(xeng_plan* pl) {
     J.full_panels = (job.n % 256) == 0;
     J.zero_first = (J.atomic_out && !job.accumulate && win.first) ? 1 : 0;
     pl->needs_fill |= J.zero_first != 0;
-    table[w] = J;
+    table.push_back(J);
   }
+  return table;
+}
+
+// Rebuild the items and the device image for the current split.
+bool build_items(xeng_plan* pl) {
+  const std::vector<QueueJob> table = job_table(pl);
+  uint8_t* image = nullptr;
+  size_t bytes = 0;
+  build_queue_image(table.data(), (int)table.size(), pl->split, &image, &bytes, pl->items);
+  if (image == nullptr) return false;
+  pl->image.assign(image, image + bytes);
+  std::free(image);
+  return true;
+}
+
+// Write the job table (inputs, flags) into the image.
+void write_jobs(xeng_plan* pl) {
+  const std::vector<QueueJob> table = job_table(pl);
+  std::memcpy(pl->image.data() + queue_jobs_offset(), table.data(),
+              sizeof(QueueJob) * table.size());
 }
 
 xeng_status upload(xeng_plan* pl, void* d_ws, hipStream_t stream) {
@@ -173,8 +137,7 @@ xeng_status launch(xeng_plan* pl, void* d_ws, hipStream_t stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return device_error(e, "plan zero fill");
   }
-  if (pl->items.empty()) return XENG_OK;
-  hipError_t e = launch_queue(d_ws, pl->grid, stream);
+  hipError_t e = launch_queues(d_ws, pl->items, pl->grid, stream);
   return e == hipSuccess ? XENG_OK : device_error(e, "plan queue launch");
 }
 
@@ -242,11 +205,14 @@ xeng_status xeng_plan_create(xeng_plan** out, const xeng_job* jobs, int njobs,
   // size the workspace for the largest split the autotuner may choose
   const int chosen = pl->split;
   pl->split = kMaxSplit;
-  build_items(pl);
+  bool ok = build_items(pl);
   pl->ws_bytes = pl->image.size();
   pl->split = chosen;
-  build_items(pl);
-  write_jobs(pl);
+  ok = ok && build_items(pl);
+  if (!ok) {
+    delete pl;
+    return fail(XENG_ENOMEM, "plan image allocation failed");
+  }
   *out = pl;
   return XENG_OK;
 }
@@ -256,7 +222,7 @@ size_t xeng_plan_workspace_bytes(const xeng_plan* plan) {
 }
 
 int64_t xeng_plan_items(const xeng_plan* plan) {
-  return plan == nullptr ? -1 : (int64_t)plan->items.size();
+  return plan == nullptr ? -1 : plan->items[0] + plan->items[1];
 }
 
 int xeng_plan_split(const xeng_plan* plan) { return plan == nullptr ? -1 : plan->split; }
@@ -356,8 +322,10 @@ xeng_status xeng_plan_autotune(xeng_plan* plan, void* d_workspace, void* hip_str
   xeng_status st = XENG_OK;
   for (int cand : candidates) {
     plan->split = cand;
-    build_items(plan);
-    write_jobs(plan);
+    if (!build_items(plan)) {
+      st = fail(XENG_ENOMEM, "plan image allocation failed");
+      break;
+    }
     if ((st = upload(plan, d_workspace, stream)) != XENG_OK) break;
     if ((st = launch(plan, d_workspace, stream)) != XENG_OK) break;   // warm-up
     (void)hipEventRecord(e0, stream);
@@ -379,8 +347,7 @@ xeng_status xeng_plan_autotune(xeng_plan* plan, void* d_workspace, void* hip_str
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   plan->split = best;
-  build_items(plan);
-  write_jobs(plan);
+  if (!build_items(plan) && st == XENG_OK) st = fail(XENG_ENOMEM, "plan image allocation failed");
   if (st == XENG_OK) st = upload(plan, d_workspace, stream);
   if (st == XENG_OK && tune_cache_path != nullptr) {
     std::ofstream outf(tune_cache_path, std::ios::app);

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -62,6 +63,7 @@ struct Slot {
   std::vector<int64_t> jobs;
   size_t frame_bytes = 0;
   std::vector<uint8_t> image;
+  int64_t items[xeng::kQueueKinds] = {0, 0};   // items of each kind in the image
 };
 
 }  // namespace
@@ -125,13 +127,11 @@ xeng_status retire(xeng_server* s) {
 }
 
 // Build the queue image for the chosen frames into slot.image; returns false
-// if it would not fit the slot.
+// if it would not fit the slot (or the host allocation failed).
 bool build_image(xeng_server* s, Slot& sl, const std::vector<std::pair<int64_t, Frame>>& picks) {
   using namespace xeng;
   const int stage = queue_stage_samples();
   const int nw = (int)picks.size();
-  std::vector<QueueItem> items;
-  std::vector<int64_t> cost;
   std::vector<QueueJob> table(nw);
   for (int w = 0; w < nw; ++w) {
     const ServerJob& J = s->jobs[picks[w].first];
@@ -151,38 +151,14 @@ bool build_image(xeng_server* s, Slot& sl, const std::vector<std::pair<int64_t, 
     q.atomic_out = 0;
     q.full_panels = (J.n % 256) == 0;
     q.zero_first = 0;
-    for (int ch = 0; ch < J.f; ++ch)
-      for (int tile = 0; tile < q.ntiles; ++tile) {
-        QueueItem it{};
-        it.job = w;
-        it.ch = ch;
-        it.tile = tile;
-        it.stage_begin = 0;
-        it.stage_end = q.total_stages;
-        items.push_back(it);
-        cost.push_back(q.total_stages);
-      }
   }
-  QueueHeader hdr{};
-  int64_t total = 0;
-  for (int64_t c : cost) total += c;
-  int part = 0;
-  int64_t acc = 0;
-  for (size_t k = 0; k < cost.size() && part < kQueueParts - 1; ++k) {
-    acc += cost[k];
-    if (acc * kQueueParts >= total * (part + 1)) hdr.part_begin[++part] = (int)k + 1;
-  }
-  while (part < kQueueParts - 1) hdr.part_begin[++part] = (int)items.size();
-  hdr.part_begin[kQueueParts] = (int)items.size();
-  hdr.jobs_offset = (int)queue_jobs_offset();
-  hdr.items_offset = (int)queue_items_offset(nw);
-  const size_t bytes = queue_items_offset(nw) + sizeof(QueueItem) * items.size();
-  if (bytes > s->slot_bytes) return false;
-  sl.image.assign(bytes, 0);
-  std::memcpy(sl.image.data(), &hdr, sizeof hdr);
-  std::memcpy(sl.image.data() + hdr.jobs_offset, table.data(), sizeof(QueueJob) * nw);
-  std::memcpy(sl.image.data() + hdr.items_offset, items.data(), sizeof(QueueItem) * items.size());
-  return true;
+  uint8_t* image = nullptr;
+  size_t bytes = 0;
+  build_queue_image(table.data(), nw, 1, &image, &bytes, sl.items);
+  const bool fits = image != nullptr && bytes <= s->slot_bytes;
+  if (fits) sl.image.assign(image, image + bytes);
+  std::free(image);
+  return fits;
 }
 
 }  // namespace
@@ -310,7 +286,7 @@ xeng_status xeng_server_step(xeng_server* s, int* launched) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(ws, sl.image.data(), sl.image.size(), hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess) e = hipEventRecord(sl.start, sl.stream);
-    if (e == hipSuccess) e = xeng::launch_queue(ws, s->grid, sl.stream);
+    if (e == hipSuccess) e = xeng::launch_queues(ws, sl.items, s->grid, sl.stream);
     if (e == hipSuccess) e = hipEventRecord(sl.end, sl.stream);
     if (e != hipSuccess) return device_error(e, "step launch");
     sl.busy = true;

@@ -131,8 +131,9 @@ def test_plan_host_logic(lib):
         jobs[k] = XengJob(base_in + k * (1 << 28), base_vis + k * (1 << 28), n, f, t, 0, 0)
     h = ctypes.c_void_p()
     assert lib.xeng_plan_create(ctypes.byref(h), jobs, 3, None) == 0
-    # 128x256 tiles reaching the upper triangle: N=256 -> 2, N=64 -> 1, N=2048 -> 72
-    assert lib.xeng_plan_items(h) == 2 * 2 + 1 * 1 + 72 * 1
+    # N <= 256 runs on the triangle kernel, one item per channel (2 + 1); N=2048
+    # on 128x256 tiles reaching the upper triangle: 72 per channel
+    assert lib.xeng_plan_items(h) == 2 + 1 + 72
     assert lib.xeng_plan_split(h) == 1
     assert lib.xeng_plan_workspace_bytes(h) > 0
     lib.xeng_plan_destroy(h)

@@ -1,0 +1,42 @@
+"""Resource checks on the compiled gfx950 kernels (host only: hipcc cross-compiles).
+
+The triangle kernel is register-tight (two waves per SIMD, up to 160 int32
+accumulators per lane): it must compile without scratch, since spill traffic in
+its stage loop would stall it on memory, and its staging and operand buffers
+must fit the 160 KiB of LDS of a gfx950 compute unit."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1503_06203_amd", "csrc")
+
+
+def device_asm(src, tmp_path):
+    from paper_1503_06203_amd import build
+    out = tmp_path / "k.s"
+    cmd = [build.HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "--cuda-device-only", "-S",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC, os.path.join(CSRC, src), "-o", str(out)]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        pytest.skip("hipcc unavailable: " + res.stderr[-300:])
+    return out.read_text()
+
+
+def kernel_field(asm, kernel, field):
+    # the .amdhsa_kernel block of the kernel holds its resource fields
+    m = re.search(r"\.amdhsa_kernel\s+\S*%s\S*(.*?)\.end_amdhsa_kernel" % kernel, asm, re.S)
+    assert m, kernel
+    f = re.search(r"\.%s\s+(\d+)" % field, m.group(1))
+    assert f, field
+    return int(f.group(1))
+
+
+def test_triangle_kernel_has_no_scratch_and_fits_lds(tmp_path):
+    asm = device_asm("xcorr_tri.hip", tmp_path)
+    assert kernel_field(asm, "xcorr_tri_kernel", "amdhsa_private_segment_fixed_size") == 0
+    for kernel in ("xcorr_tri_kernel", "xcorr_tri_queue_kernel"):
+        assert kernel_field(asm, kernel, "amdhsa_group_segment_fixed_size") <= 160 * 1024
