@@ -373,18 +373,29 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_kernel(TriParams p) {
 // last workgroup out resets the counters for the next launch. Each wave picks
 // its block program once and runs the item loop with it (all waves meet at the
 // same barriers), so no program's set-up is live in another's loop.
+// Queue state that only thread 0 touches lives in LDS, and the header, job
+// and item pointers are rederived from the kernel arguments per item, so that
+// none of it occupies scalar registers while a channel is computed (the
+// channel code needs nearly all of them).
+struct QueueCursor {
+  int next_item;
+  int part;    // sub-queue being served
+  int tried;   // sub-queues found empty so far
+};
+
 template <class Prog>
 __device__ __forceinline__ void tri_queue_loop(uint8_t* ws, int hdr_offset, int base,
                                                uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
-                                               uint8_t* dec_n, int* next_item) {
-  QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws + hdr_offset);
-  const QueueHeaderC hdr_c = (QueueHeaderC)(ws + hdr_offset);
-  const QueueJobC jobs = (QueueJobC)(ws + hdr_c->jobs_offset);
-  const QueueItemC items = (QueueItemC)(ws + hdr_c->items_offset);
-  int part = blockIdx.x % kQueueParts, tried = 0;
+                                               uint8_t* dec_n, QueueCursor* qc) {
+  if (threadIdx.x == 0) {
+    qc->part = blockIdx.x % kQueueParts;
+    qc->tried = 0;
+  }
   while (true) {
     if (threadIdx.x == 0) {
-      int it = -1;
+      QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws + hdr_offset);
+      const QueueHeaderC hdr_c = (QueueHeaderC)(ws + hdr_offset);
+      int part = qc->part, tried = qc->tried, it = -1;
       while (tried < kQueueParts) {
         const int b = hdr_c->part_begin[part], e = hdr_c->part_begin[part + 1];
         if (b < e) {
@@ -397,14 +408,17 @@ __device__ __forceinline__ void tri_queue_loop(uint8_t* ws, int hdr_offset, int 
         part = (part + 1) % kQueueParts;
         ++tried;
       }
-      *next_item = it;
+      qc->part = part;
+      qc->tried = tried;
+      qc->next_item = it;
     }
     __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(*next_item);
+    const int it = __builtin_amdgcn_readfirstlane(qc->next_item);
     __syncthreads();
     if (it < 0) break;
-    const QueueItem q = load_item(items, it);
-    const QueueJob J = load_job(jobs, q.job);
+    const QueueHeaderC hdr_c = (QueueHeaderC)(ws + hdr_offset);
+    const QueueItem q = load_item((QueueItemC)(ws + hdr_c->items_offset), it);
+    const QueueJob J = load_job((QueueJobC)(ws + hdr_c->jobs_offset), q.job);
     TriParams p;
     p.in = J.in;
     p.vis = J.vis;
@@ -422,6 +436,7 @@ __device__ __forceinline__ void tri_queue_loop(uint8_t* ws, int hdr_offset, int 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws + hdr_offset);
     __threadfence();
     const unsigned d = atomicAdd(&hdr->done, 1u);
     if (d == gridDim.x - 1) {
@@ -438,17 +453,17 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_queue_kernel(uint8_t* w
   __shared__ __attribute__((aligned(16))) uint8_t raw1[kRawBytes];
   __shared__ __attribute__((aligned(16))) uint8_t dec_p[kGroups * kPGroup];
   __shared__ __attribute__((aligned(16))) uint8_t dec_n[kGroups * kNGroup];
-  __shared__ int next_item;
+  __shared__ QueueCursor qc;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int simd = wave & 3;
   if (wave < 4) {
-    tri_queue_loop<ProgA>(ws, hdr_offset, simd, raw0, raw1, dec_p, dec_n, &next_item);
+    tri_queue_loop<ProgA>(ws, hdr_offset, simd, raw0, raw1, dec_p, dec_n, &qc);
   } else {
     switch (simd) {
-      case 0: tri_queue_loop<ProgB<0>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &next_item); break;
-      case 1: tri_queue_loop<ProgB<1>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &next_item); break;
-      case 2: tri_queue_loop<ProgB<2>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &next_item); break;
-      default: tri_queue_loop<ProgB<3>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &next_item); break;
+      case 0: tri_queue_loop<ProgB<0>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &qc); break;
+      case 1: tri_queue_loop<ProgB<1>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &qc); break;
+      case 2: tri_queue_loop<ProgB<2>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &qc); break;
+      default: tri_queue_loop<ProgB<3>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &qc); break;
     }
   }
 }
