@@ -9,10 +9,22 @@
 //   * 8 waves, two per SIMD. SIMD s owns block rows s and 7-s: (8-s) + (s+1)
 //     = 9 blocks, so the four SIMDs carry equal MFMA work. The SIMD's first
 //     wave takes row s, columns s..s+4; its second wave the other four blocks.
+//   * the matrix cores multiply the Excess-8 fields themselves, u = x + 8 in
+//     [0, 15] (the offset arithmetic of Sec. III-A, Eq. 3), not the signed
+//     values: with a, b the fields (Re, Im) of element i and c, d those of j,
+//       Re V_ij = sum(a c + b d) - 8 (SR_i + SI_i) - 8 (SR_j + SI_j) + 128 T
+//       Im V_ij = sum(b c + a' d) + 8 SR_i - 8 SI_i - 8 SR_j - 7 SI_j,
+//     a' = 15 - a, SR_e and SI_e the sums of element e's fields, T the number
+//     of samples. On realistic data int8 MFMA throughput is power-limited, and
+//     operands whose upper four bits never toggle run about 13 % faster than
+//     sign-extended ones. The byte 0x00 (the padding the loads produce past
+//     the end of the data) then adds nothing to any sum, so no sample masks
+//     are needed; the uncorrected sums may wrap in int32, but the arithmetic
+//     is exact modulo 2^32 and the corrected result fits.
 //   * every operand, row or column, is decoded once per workgroup into LDS
-//     slabs P = [Re g, Re g+1, Im g, Im g+1] and N = [-Re g, -Re g+1] (each
-//     dword = 4 consecutive samples of one component). Q is the upper half of
-//     P followed by N, so the MFMA loop itself does no decode work.
+//     slabs P = [a g, a g+1, b g, b g+1] and N = [a' g, a' g+1] (each dword = 4
+//     consecutive samples of one field). Q = [b g, b g+1, a' g, a' g+1] is the
+//     upper half of P followed by N, so the MFMA loop does no decode work.
 //   * packed bytes go from HBM straight into LDS (buffer_load ... lds), two
 //     stages ahead of use. Each wave loads 8 sample rows per stage and is the
 //     only reader of them: it waits for its own loads only, and the stage
@@ -140,11 +152,6 @@ __device__ inline void vm_wait() {
   asm volatile("" ::: "memory");
 }
 
-// Keep the first `valid` bytes (samples) of w, turn the rest into zero samples.
-__device__ inline uint32_t keep_samples(uint32_t w, int valid) {
-  const uint32_t m = valid >= 4 ? 0xFFFFFFFFu : (valid <= 0 ? 0u : (1u << (8 * valid)) - 1u);
-  return (w & m) | (kZeroSamples & ~m);
-}
 
 template <class Prog>
 __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, int sb, int se,
@@ -160,14 +167,16 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   // ---- loads: this wave fetches sample rows 8*wave .. 8*wave+7 of a stage; a
   // lane carries four elements. Every stage issues exactly 8 loads per wave
   // (the waits below count on it): the buffer descriptor's record count ends
-  // at t_end, so rows past it read nothing (their samples are masked in the
-  // decode), and lanes past n use an offset beyond every record.
+  // at the end of this workgroup's samples (t_end, or the end of stage se), so
+  // rows past it read nothing and stay 0x00, which adds nothing; lanes past n
+  // use an offset beyond every record.
   const uint32_t voff = (4 * lane < n) ? 4u * (uint32_t)lane : kOob;
+  const int t_stop = min(p.t_end, p.t0 + se * kStage);   // samples [t0 + sb*64, t_stop)
   auto fetch = [&](uint8_t* raw, int st) {
     // a sample index (< 2^25) that is uniform across the wave; saying so keeps
     // the buffer descriptor in scalar registers
     const int first = __builtin_amdgcn_readfirstlane(p.t0 + st * kStage + 8 * wave);
-    const int64_t bytes = (int64_t)(p.t_end - first) * n;
+    const int64_t bytes = (int64_t)(t_stop - first) * n;
     const int records = bytes <= 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : (int)bytes);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(chan + (int64_t)first * n), 0, records, 0x00020000);
@@ -189,15 +198,18 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   auto tr_read = [&](const uint8_t* raw, int i) {
     return __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i_ptr)(raw + tr_off + 64 * i));
   };
-  auto decode = [&](v2i w, int buf, int i, int valid) {
-    const uint32_t a = keep_samples((uint32_t)w.x, valid);
-    const uint32_t b = keep_samples((uint32_t)w.y, valid - 4);
-    const uint32_t ha = fields_hi(a), hb = fields_hi(b);
-    const v4i ps = {(int)fields_to_s8(ha), (int)fields_to_s8(hb), (int)fields_to_s8(fields_lo(a)),
-                    (int)fields_to_s8(fields_lo(b))};
-    const v2i ns = {(int)fields_to_neg_s8(ha), (int)fields_to_neg_s8(hb)};
+  // Field sums of the lane's elements 64*i + lane over this wave's samples.
+  uint32_t sum_re[4] = {0, 0, 0, 0}, sum_im[4] = {0, 0, 0, 0};
+  auto decode = [&](v2i w, int buf, int i) {
+    const uint32_t ra = fields_hi((uint32_t)w.x), rb = fields_hi((uint32_t)w.y);
+    const uint32_t ia = fields_lo((uint32_t)w.x), ib = fields_lo((uint32_t)w.y);
+    const v4i ps = {(int)ra, (int)rb, (int)ia, (int)ib};
+    const v2i ns = {(int)(ra ^ 0x0F0F0F0Fu), (int)(rb ^ 0x0F0F0F0Fu)};
     *reinterpret_cast<v4i*>(wr_p + buf * kPBuf + i * 1024) = ps;
     *reinterpret_cast<v2i*>(wr_n + buf * kNBuf + i * 512) = ns;
+    // v_sad_u8 against zero adds the four bytes of a word
+    sum_re[i] = __builtin_amdgcn_sad_u8(rb, 0u, __builtin_amdgcn_sad_u8(ra, 0u, sum_re[i]));
+    sum_im[i] = __builtin_amdgcn_sad_u8(ib, 0u, __builtin_amdgcn_sad_u8(ia, 0u, sum_im[i]));
   };
 
   // ---- MFMA operands: lane half h reads group 2*ks + h, element 32*block + l32
@@ -236,20 +248,14 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     }
   };
 
-  // samples of this wave's group of stage st that lie before t_end
-  auto group_valid = [&](int st) {
-    const int v = __builtin_amdgcn_readfirstlane(p.t_end - (p.t0 + st * kStage + 8 * wave));
-    return v < 0 ? 0 : (v > 8 ? 8 : v);
-  };
-
   // One stage st, software-pipelined: the step-0 fragments are requested
   // first, then this wave's loads for st+2 and the transposing reads of its
   // rows of st+1; each MFMA step then requests the next step's fragments and
   // overlaps its MFMAs with the decode of one quarter of the elements of st+1
   // (written to the other operand buffer). kPar = (st - sb) & 1 selects the
-  // static buffers. Stages past se are fetched and decoded as well (rows past
-  // t_end read nothing and decode to zero samples; within t_end they are
-  // simply not used): every stage is the same straight-line code.
+  // static buffers. Stages past se are fetched and decoded as well (their rows
+  // read nothing: zero bytes, which add nothing to the products or the field
+  // sums): every stage is the same straight-line code.
   auto body = [&](auto par, int st) {
     constexpr int kPar = decltype(par)::value;
     uint8_t* const raw_ld = kPar ? raw1 : raw0;
@@ -258,14 +264,13 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     load_frags(fr[0], kPar, 0);
     fetch(raw_ld, st + 2);
     vm_wait<8>();   // all but the 8 loads just issued are done: rows of st+1 are in LDS
-    const int valid = group_valid(st + 1);
     v2i rawv[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) rawv[i] = tr_read(raw_dc, i);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       if (ks < 3) load_frags(fr[(ks + 1) & 1], kPar, ks + 1);
-      decode(rawv[ks], kPar ^ 1, ks, valid);
+      decode(rawv[ks], kPar ^ 1, ks);
       mfma_step(fr[ks & 1]);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -276,11 +281,8 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   fetch(raw0, sb);
   fetch(raw1, sb + 1);
   vm_wait<8>();
-  {
-    const int valid = group_valid(sb);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) decode(tr_read(raw0, i), 0, i, valid);
-  }
+  for (int i = 0; i < 4; ++i) decode(tr_read(raw0, i), 0, i);
   lds_barrier();
 
   int st = sb;
@@ -290,8 +292,39 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   }
   if (st < se) body(std::integral_constant<int, 0>{}, st);
   // loads issued for the two stages past se may still be writing LDS: let
-  // them land before the workgroup moves on (or ends and releases its LDS)
+  // them land (in every wave) before the raw buffers are reused below and
+  // before the workgroup moves on or ends and releases its LDS
   vm_wait<0>();
+  lds_barrier();
+
+  // ---- offset corrections: per element e, from the field sums of all waves,
+  // cr_e = 8 (SR_e + SI_e), ci_row_e = 8 (SR_e - SI_e), ci_col_e = 8 SR_e + 7 SI_e
+  {
+    uint32_t* part = reinterpret_cast<uint32_t*>(raw0);   // [wave][re, im][element]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      part[(2 * wave) * kElems + 64 * i + lane] = sum_re[i];
+      part[(2 * wave + 1) * kElems + 64 * i + lane] = sum_im[i];
+    }
+  }
+  lds_barrier();
+  int32_t* const corr = reinterpret_cast<int32_t*>(raw1);   // [cr, ci_row, ci_col][element]
+  if (tid < kElems) {
+    const uint32_t* part = reinterpret_cast<const uint32_t*>(raw0);
+    uint32_t sr = 0, si = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+      sr += part[(2 * w) * kElems + tid];
+      si += part[(2 * w + 1) * kElems + tid];
+    }
+    corr[tid] = (int32_t)(8u * (sr + si));
+    corr[kElems + tid] = (int32_t)(8u * (sr - si));
+    corr[2 * kElems + tid] = (int32_t)(8u * sr + 7u * si);
+  }
+  lds_barrier();
+  // samples this workgroup summed (stages sb..se-1 within t_end)
+  const int t_sum = max(0, t_stop - (p.t0 + sb * kStage));
+  const uint32_t re_const = 128u * (uint32_t)t_sum;
 
   // ---- epilogue: masked writes of i <= j < n into the packed triangle ------------
   const int64_t n64 = n;
@@ -303,12 +336,17 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     for (int s = 0; s < kNS; ++s) {
       const int rb = base + Prog::p[Prog::sa[s]], cb = base + Prog::p[Prog::sb[s]];
       const int j = 32 * cb + l32;
+      const uint32_t re_j = re_const - (uint32_t)corr[j];
+      const uint32_t ci_col_j = (uint32_t)corr[2 * kElems + j];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = 32 * rb + 8 * (r >> 2) + 4 * half + (r & 3);
         if (i <= j && j < n) {
           int32_t* o = out + 2 * tri_index(n64, i, j);
-          const int re = acc_re[s][r], im = acc_im[s][r];
+          // int32 arithmetic modulo 2^32 (unsigned): exact for the result
+          const int re = (int)((uint32_t)acc_re[s][r] + re_j - (uint32_t)corr[i]);
+          const int im =
+              (int)((uint32_t)acc_im[s][r] + (uint32_t)corr[kElems + i] - ci_col_j);
           if (kMode == 2) {
             atomicAdd(o, re);
             atomicAdd(o + 1, im);

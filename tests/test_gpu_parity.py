@@ -199,6 +199,18 @@ def test_tri_accumulate_and_many_channels():
     assert_same(both, oracle.correlate(x.numpy()))
 
 
+def test_tri_offset_sums_wrap_exactly():
+    # The triangle kernel multiplies the 4-bit fields (0..15) and subtracts
+    # field sums afterwards. With every byte 0xFF over the longest allowed
+    # integration in one workgroup, the uncorrected sums (450 per sample) wrap
+    # int32 three times; the corrected result, 98 per sample, does not.
+    import paper_1503_06203_amd as xe
+    t = xe.MAX_SAMPLES
+    x = synth.constant_bytes(1, t, 8, 0xFF, device=DEV)
+    vis = gpu_correlate(x, variant=TRI_VARIANT, split=1).cpu().numpy()
+    assert (vis[..., 0] == 98 * t).all() and (vis[..., 1] == 0).all()
+
+
 def test_tri_constant_extremes_exercise_masking():
     # 0x00 decodes to (-8,-8); any padded sample read as 0x00 instead of a
     # zero sample would add 128 per entry
