@@ -134,6 +134,25 @@ __device__ inline void decode_rows_half(const uint32_t x0[4], const uint32_t x1[
   }
 }
 
+// Offset form of the row slabs (8-wave kernel): the Excess-8 fields
+// themselves, [uRe g, uRe g+1, uIm g, uIm g+1]; their sums per element are
+// added into sums[0][e] (Re) and sums[1][e] (Im) in LDS (atomic adds: the
+// lanes of the four K steps and two lane halves add into the same element).
+__device__ inline void decode_rows_fields(const uint32_t x0[4], const uint32_t x1[4], int part,
+                                          uint8_t* pslab, int quad_base, uint32_t* sums) {
+#pragma unroll
+  for (int kq = 0; kq < 2; ++kq) {
+    const int k = 2 * part + kq;
+    const int slot = slot_swizzle(quad_base + k);
+    const uint32_t r0 = fields_hi(x0[k]), r1 = fields_hi(x1[k]);
+    const uint32_t i0 = fields_lo(x0[k]), i1 = fields_lo(x1[k]);
+    *reinterpret_cast<v4i*>(pslab + slot * 16) = v4i{(int)r0, (int)r1, (int)i0, (int)i1};
+    atomicAdd(sums + quad_base + k, __builtin_amdgcn_sad_u8(r1, 0u, __builtin_amdgcn_sad_u8(r0, 0u, 0u)));
+    atomicAdd(sums + kRows + quad_base + k,
+              __builtin_amdgcn_sad_u8(i1, 0u, __builtin_amdgcn_sad_u8(i0, 0u, 0u)));
+  }
+}
+
 // Column (B) side: 16 raw rows of the lane's quad go to LDS unchanged.
 __device__ inline void write_cols_raw(const uint32_t* rows16, uint8_t* dst) {
 #pragma unroll
@@ -480,6 +499,14 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
       acc_im[rb][cb] = v16i{};
     }
 
+  // Field sums for the offset corrections: row waves add the fields of their
+  // row quads into row_sums in LDS as they decode; MFMA waves sum those of
+  // their columns in registers (the two lane halves hold the two K halves).
+  uint32_t* const row_sums = reinterpret_cast<uint32_t*>(lds + 2 * kBufBytes);   // [re, im][128]
+  uint32_t col_sr[2] = {0, 0}, col_si[2] = {0, 0};
+  for (int e = tid; e < 2 * kRows; e += kThreads8) row_sums[e] = 0u;
+  __syncthreads();
+
   struct Frags {
     v4i pa[2];
     v2i rb[2];
@@ -495,17 +522,23 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
           (__attribute__((address_space(3))) v2i*)(base + b_off + kk * 16 * kColRowStride +
                                                    cb * 32));
   };
+  // Offset arithmetic (Sec. III-A, Eq. 3) on the Excess-8 fields u in [0, 15]:
+  // P = [uRe, uIm] both sides, Q = [uIm, 15 - uRe] on the row side; the field
+  // sums correct the products in the epilogue.
   auto mfma_step = [&](const Frags& fr) {
     v4i pb[2];
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
       const uint32_t lo = (uint32_t)fr.rb[cb].x, hi = (uint32_t)fr.rb[cb].y;
-      pb[cb] = v4i{(int)re16(lo), (int)re16(hi), (int)im16(lo), (int)im16(hi)};
+      const uint32_t rl = fields_hi(lo), rh = fields_hi(hi), il = fields_lo(lo), ih = fields_lo(hi);
+      pb[cb] = v4i{(int)rl, (int)rh, (int)il, (int)ih};
+      col_sr[cb] = __builtin_amdgcn_sad_u8(rh, 0u, __builtin_amdgcn_sad_u8(rl, 0u, col_sr[cb]));
+      col_si[cb] = __builtin_amdgcn_sad_u8(ih, 0u, __builtin_amdgcn_sad_u8(il, 0u, col_si[cb]));
     }
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
-      const v4i qa = {fr.pa[rb].z, fr.pa[rb].w, (int)neg_s8((uint32_t)fr.pa[rb].x),
-                      (int)neg_s8((uint32_t)fr.pa[rb].y)};
+      const v4i qa = {fr.pa[rb].z, fr.pa[rb].w, (int)((uint32_t)fr.pa[rb].x ^ 0x0F0F0F0Fu),
+                      (int)((uint32_t)fr.pa[rb].y ^ 0x0F0F0F0Fu)};
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
         acc_re[rb][cb] =
@@ -530,7 +563,7 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
         } else {
           const bool ok = row_ok && r + 8 * half < valid;
           const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_row : kOob, r * n, 0);
-          raw.w[r] = ok ? v : kZeroSamples;
+          raw.w[r] = ok ? v : 0u;
         }
       }
     } else {
@@ -541,7 +574,7 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
         } else {
           const bool ok = col_ok && r < valid;
           const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_col : kOob, r * n, 0);
-          raw.w[r] = ok ? v : kZeroSamples;
+          raw.w[r] = ok ? v : 0u;
         }
       }
     }
@@ -557,8 +590,8 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
     auto slice = [&](int seg, Raw16& dec, int buf, uint32_t* tx0, uint32_t* tx1) {
       if (kRow) {
         if (seg == 1) transpose_rows(dec.w, tx0, tx1);
-        if (seg == 2) decode_rows_half(tx0, tx1, 0, row_dst0 + buf * kBufBytes, 4 * l32);
-        if (seg == 3) decode_rows_half(tx0, tx1, 1, row_dst0 + buf * kBufBytes, 4 * l32);
+        if (seg == 2) decode_rows_fields(tx0, tx1, 0, row_dst0 + buf * kBufBytes, 4 * l32, row_sums);
+        if (seg == 3) decode_rows_fields(tx0, tx1, 1, row_dst0 + buf * kBufBytes, 4 * l32, row_sums);
       } else {
         uint8_t* dst = col_dst0 + buf * kBufBytes;
         if (seg == 1) {
@@ -633,21 +666,37 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
     else run(std::false_type{}, std::false_type{});
   }
 
+  // ---- offset corrections -------------------------------------------------------
+  // per row element of the tile: 8 (SR + SI) and 8 (SR - SI), from row_sums;
+  // per column: 8 (SR + SI) and 8 SR + 7 SI, from this wave's column sums.
+  // The last stage ended with a barrier, so row_sums is complete.
   if (!wave_active) return;
+  // samples this tile summed: stages [stage_begin, stage_end) within t_end
+  const int64_t t_first = p.t0 + (int64_t)stage_begin * kStage;
+  const int64_t t_last = min((int64_t)p.t_end, p.t0 + (int64_t)stage_end * kStage);
+  const uint32_t re_const = 128u * (uint32_t)max((int64_t)0, t_last - t_first);
   const int64_t n64 = n;
   const int64_t entries = n64 * (n64 + 1) / 2;
   int32_t* out = p.vis + (int64_t)ch * entries * 2;
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+  for (int cb = 0; cb < 2; ++cb) {
+    const uint32_t csr = col_sr[cb] + (uint32_t)__shfl_xor((int)col_sr[cb], 32);
+    const uint32_t csi = col_si[cb] + (uint32_t)__shfl_xor((int)col_si[cb], 32);
+    const uint32_t re_j = re_const - 8u * (csr + csi);
+    const uint32_t ci_j = 8u * csr + 7u * csi;
+    const int j = col0 + wc * 64 + cb * 32 + l32;
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int j = col0 + wc * 64 + cb * 32 + l32;
+    for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int i = row0 + wr * 64 + rb * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int il = wr * 64 + rb * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int i = row0 + il;
         if (i <= j && j < n) {
           int32_t* o = out + 2 * tri_index(n64, i, j);
-          const int re = acc_re[rb][cb][r] >> 4, im = acc_im[rb][cb][r] >> 4;
+          // int32 arithmetic modulo 2^32: the uncorrected sums may wrap
+          const uint32_t sr = row_sums[il], si = row_sums[kRows + il];
+          const int re = (int)((uint32_t)acc_re[rb][cb][r] + re_j - 8u * (sr + si));
+          const int im = (int)((uint32_t)acc_im[rb][cb][r] + 8u * (sr - si) - ci_j);
           if (p.atomic_out) {
             atomicAdd(o, re);
             atomicAdd(o + 1, im);
@@ -660,9 +709,10 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
         }
       }
     }
+  }
 }
 __global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes + 2 * kRows * 4];
   // With two waves per SIMD each wave has 256 registers. An AGPR operand here
   // tells the compiler the kernel uses accumulation registers, so it splits
   // them 128 VGPR + 128 AGPR and keeps the 128 accumulators out of the VGPRs.
@@ -688,7 +738,7 @@ __global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p)
 // resets the counters, so the workspace is ready for the next launch (no
 // memset, which keeps the launch capturable in a graph).
 __global__ __launch_bounds__(kThreads8, 1) void xcorr_queue_kernel(uint8_t* ws, int hdr_offset) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes + 2 * kRows * 4];
   __shared__ int next_item;
   asm volatile("; accumulators live in AGPRs" ::"a"(0));
   QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws + hdr_offset);
