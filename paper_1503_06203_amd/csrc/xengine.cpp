@@ -41,20 +41,19 @@ int device_cu_count() {
   return cus > 0 ? cus : 256;
 }
 
-int tri_auto_split(int f, int64_t t_count, int cus) {
+int auto_split(int64_t units, int64_t stages, int cus) {
   // Cost model in stage times: rounds of workgroups x (stages per workgroup +
-  // a fixed cost for the prologue and the output writes, plus the atomic
-  // combine when split). A split keeps at least 16 stages per workgroup.
-  const int64_t stage = tri_stage_samples();
-  const int64_t stages = (t_count + stage - 1) / stage;
+  // a fixed cost for the prologue and the output writes, larger when the
+  // time axis is split: atomic adds and the zero fill). A split keeps at
+  // least 16 stages per workgroup.
   if (cus < 1) cus = 1;
   int best = 1;
   double best_cost = 0.0;
   for (int split = 1; split <= 64; ++split) {
     if (split > 1 && stages / split < 16) break;
-    const int64_t wgs = (int64_t)f * split;
+    const int64_t wgs = units * split;
     const int64_t rounds = (wgs + cus - 1) / cus;
-    const double per_wg = (double)((stages + split - 1) / split) + (split > 1 ? 6.0 : 4.0);
+    const double per_wg = (double)((stages + split - 1) / split) + (split > 1 ? 8.0 : 4.0);
     const double cost = (double)rounds * per_wg;
     if (split == 1 || cost < best_cost * 0.97) {
       best = split;
@@ -62,6 +61,18 @@ int tri_auto_split(int f, int64_t t_count, int cus) {
     }
   }
   return best;
+}
+
+int tri_auto_split(int f, int64_t t_count, int cus) {
+  const int64_t stage = tri_stage_samples();
+  return auto_split(f, (t_count + stage - 1) / stage, cus);
+}
+
+int wide_auto_split(int n, int f, int64_t t_count, int cus) {
+  const int64_t stage = queue_stage_samples();
+  const int64_t win = wide_max_samples_per_launch();
+  const int64_t t_launch = t_count < win ? t_count : win;   // one launch window
+  return auto_split(wide_tiles_per_channel(n) * f, (t_launch + stage - 1) / stage, cus);
 }
 
 }  // namespace xeng
@@ -189,6 +200,8 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
   int split = split_t > 0 ? split_t : 1;
   if (variant == kVariantTri && split_t == 0)
     split = xeng::tri_auto_split(f, t, xeng::device_cu_count());
+  if (variant == kVariantWide8 && split_t == 0)
+    split = xeng::wide_auto_split(n, f, t, xeng::device_cu_count());
   if (split > 1 && !accumulate) {
     hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
     if (e != hipSuccess) return device_error(e, "zero fill");
@@ -221,7 +234,9 @@ xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* var
   const bool aligned = input_aligned != 0 && n % 4 == 0;
   const int v = default_variant(n, aligned);
   *variant = v;
-  *split_t = (v == kVariantTri && t > 0) ? xeng::tri_auto_split(f, t, xeng::device_cu_count()) : 1;
+  *split_t = 1;
+  if (v == kVariantTri && t > 0) *split_t = xeng::tri_auto_split(f, t, xeng::device_cu_count());
+  if (v == kVariantWide8 && t > 0) *split_t = xeng::wide_auto_split(n, f, t, xeng::device_cu_count());
   return XENG_OK;
 }
 

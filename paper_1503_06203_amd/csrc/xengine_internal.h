@@ -19,8 +19,12 @@ xeng_status check_job(const uint8_t* d_in, const int32_t* d_vis, int n, int f, i
                       int64_t t_prev, int accumulate, size_t* in_bytes, size_t* vis_bytes);
 // Compute units of the current device (256 if the query fails).
 int device_cu_count();
-// Time split for the triangle kernel: f * split workgroups of one channel's
-// stages each, chosen to fill `cus` compute units in whole rounds.
+// Time split: `units` workgroups per split step (channels, or tiles of all
+// channels) over `stages` stages, chosen to fill `cus` compute units in whole
+// rounds.
+int auto_split(int64_t units, int64_t stages, int cus);
+// The split for the triangle kernel and for the 8-wave wide kernel.
 int tri_auto_split(int f, int64_t t_count, int cus);
+int wide_auto_split(int n, int f, int64_t t_count, int cus);
 
 }  // namespace xeng
