@@ -22,9 +22,9 @@
 //     are needed; the uncorrected sums may wrap in int32, but the arithmetic
 //     is exact modulo 2^32 and the corrected result fits.
 //   * every operand, row or column, is decoded once per workgroup into LDS
-//     slabs P = [a g, a g+1, b g, b g+1] and N = [a' g, a' g+1] (each dword = 4
-//     consecutive samples of one field). Q = [b g, b g+1, a' g, a' g+1] is the
-//     upper half of P followed by N, so the MFMA loop does no decode work.
+//     slabs P = [a g, a g+1, b g, b g+1] (each dword = 4 consecutive samples
+//     of one field). Q = [b g, b g+1, a' g, a' g+1] is formed from P in
+//     registers (a' = a XOR 15: one op per dword).
 //   * packed bytes go from HBM straight into LDS (buffer_load ... lds), two
 //     stages ahead of use. Each wave loads 8 sample rows per stage and is the
 //     only reader of them: it waits for its own loads only, and the stage
@@ -53,9 +53,7 @@ constexpr int kStage = 64;                      // samples per stage
 constexpr int kRawStride = kElems + 32;         // LDS bytes per raw sample row (bank spread)
 constexpr int kRawBytes = kStage * kRawStride;  // 18 KiB per raw buffer
 constexpr int kPBuf = kElems * 16;              // P slabs of one 8-sample group, one buffer
-constexpr int kNBuf = kElems * 8;               // N slabs of one group, one buffer
 constexpr int kPGroup = 2 * kPBuf;              // a group's slabs in both buffers
-constexpr int kNGroup = 2 * kNBuf;
 constexpr int kGroups = kStage / 8;             // 8-sample groups per stage (= waves)
 constexpr uint32_t kOob = 0x80000000u;          // buffer offset past every record: load returns 0
 
@@ -76,52 +74,41 @@ struct TriParams {
 // A wave's share of the 8x8 block triangle, relative to its base block (the
 // SIMD index for the first wave of a SIMD, 0 for the second):
 //   p[]  blocks whose P slabs the wave reads each MFMA step (A and B sides)
-//   nq[] blocks whose N slabs it reads (the rows it multiplies as A)
-//   slot k computes block (p[sa[k]], p[sb[k]]) with N slabs nq[sn[k]].
+//   slot k computes block (p[sa[k]], p[sb[k]]).
 struct ProgA {  // row s, columns s..s+4
-  static constexpr int kNP = 5, kNN = 1, kNS = 5;
+  static constexpr int kNP = 5, kNS = 5;
   static constexpr int p[kNP] = {0, 1, 2, 3, 4};
-  static constexpr int nq[kNN] = {0};
   static constexpr int sa[kNS] = {0, 0, 0, 0, 0};
-  static constexpr int sn[kNS] = {0, 0, 0, 0, 0};
   static constexpr int sb[kNS] = {0, 1, 2, 3, 4};
 };
 template <int S>
 struct ProgB;
 template <>
 struct ProgB<0> {  // (0,5) (0,6) (0,7) (7,7)
-  static constexpr int kNP = 4, kNN = 2, kNS = 4;
+  static constexpr int kNP = 4, kNS = 4;
   static constexpr int p[kNP] = {0, 5, 6, 7};
-  static constexpr int nq[kNN] = {0, 7};
   static constexpr int sa[kNS] = {0, 0, 0, 3};
-  static constexpr int sn[kNS] = {0, 0, 0, 1};
   static constexpr int sb[kNS] = {1, 2, 3, 3};
 };
 template <>
 struct ProgB<1> {  // (1,6) (1,7) (6,6) (6,7)
-  static constexpr int kNP = 3, kNN = 2, kNS = 4;
+  static constexpr int kNP = 3, kNS = 4;
   static constexpr int p[kNP] = {1, 6, 7};
-  static constexpr int nq[kNN] = {1, 6};
   static constexpr int sa[kNS] = {0, 0, 1, 1};
-  static constexpr int sn[kNS] = {0, 0, 1, 1};
   static constexpr int sb[kNS] = {1, 2, 1, 2};
 };
 template <>
 struct ProgB<2> {  // (2,7) (5,5) (5,6) (5,7)
-  static constexpr int kNP = 4, kNN = 2, kNS = 4;
+  static constexpr int kNP = 4, kNS = 4;
   static constexpr int p[kNP] = {2, 5, 6, 7};
-  static constexpr int nq[kNN] = {2, 5};
   static constexpr int sa[kNS] = {0, 1, 1, 1};
-  static constexpr int sn[kNS] = {0, 1, 1, 1};
   static constexpr int sb[kNS] = {3, 1, 2, 3};
 };
 template <>
 struct ProgB<3> {  // (4,4) (4,5) (4,6) (4,7)
-  static constexpr int kNP = 4, kNN = 1, kNS = 4;
+  static constexpr int kNP = 4, kNS = 4;
   static constexpr int p[kNP] = {4, 5, 6, 7};
-  static constexpr int nq[kNN] = {4};
   static constexpr int sa[kNS] = {0, 0, 0, 0};
-  static constexpr int sn[kNS] = {0, 0, 0, 0};
   static constexpr int sb[kNS] = {0, 1, 2, 3};
 };
 
@@ -155,9 +142,8 @@ __device__ inline void vm_wait() {
 
 template <class Prog>
 __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, int sb, int se,
-                                        uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
-                                        uint8_t* dec_n) {
-  constexpr int kNP = Prog::kNP, kNN = Prog::kNN, kNS = Prog::kNS;
+                                        uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p) {
+  constexpr int kNP = Prog::kNP, kNS = Prog::kNS;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int half = lane >> 5, l32 = lane & 31;
@@ -194,7 +180,6 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   const int lq = lane & 15;
   const int tr_off = (8 * wave + (lq >> 1)) * kRawStride + 16 * ((lane >> 4) & 3) + 8 * (lq & 1);
   uint8_t* const wr_p = dec_p + wave * kPGroup + lane * 16;
-  uint8_t* const wr_n = dec_n + wave * kNGroup + lane * 8;
   auto tr_read = [&](const uint8_t* raw, int i) {
     return __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i_ptr)(raw + tr_off + 64 * i));
   };
@@ -204,9 +189,7 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     const uint32_t ra = fields_hi((uint32_t)w.x), rb = fields_hi((uint32_t)w.y);
     const uint32_t ia = fields_lo((uint32_t)w.x), ib = fields_lo((uint32_t)w.y);
     const v4i ps = {(int)ra, (int)rb, (int)ia, (int)ib};
-    const v2i ns = {(int)(ra ^ 0x0F0F0F0Fu), (int)(rb ^ 0x0F0F0F0Fu)};
     *reinterpret_cast<v4i*>(wr_p + buf * kPBuf + i * 1024) = ps;
-    *reinterpret_cast<v2i*>(wr_n + buf * kNBuf + i * 512) = ns;
     // v_sad_u8 against zero adds the four bytes of a word
     sum_re[i] = __builtin_amdgcn_sad_u8(rb, 0u, __builtin_amdgcn_sad_u8(ra, 0u, sum_re[i]));
     sum_im[i] = __builtin_amdgcn_sad_u8(ib, 0u, __builtin_amdgcn_sad_u8(ia, 0u, sum_im[i]));
@@ -214,7 +197,6 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
 
   // ---- MFMA operands: lane half h reads group 2*ks + h, element 32*block + l32
   const uint8_t* const rd_p = dec_p + half * kPGroup + (32 * base + l32) * 16;
-  const uint8_t* const rd_n = dec_n + half * kNGroup + (32 * base + l32) * 8;
   v16i acc_re[kNS], acc_im[kNS];
 #pragma unroll
   for (int s = 0; s < kNS; ++s) {
@@ -224,24 +206,19 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   // Operand fragments of one 16-sample MFMA step.
   struct Frags {
     v4i pf[kNP];
-    v2i nf[kNN];
   };
   auto load_frags = [&](Frags& fr, int buf, int ks) {
 #pragma unroll
     for (int k = 0; k < kNP; ++k)
       fr.pf[k] = *reinterpret_cast<const v4i*>(rd_p + ks * 2 * kPGroup + buf * kPBuf +
                                                Prog::p[k] * 512);
-#pragma unroll
-    for (int k = 0; k < kNN; ++k)
-      fr.nf[k] = *reinterpret_cast<const v2i*>(rd_n + ks * 2 * kNGroup + buf * kNBuf +
-                                               Prog::nq[k] * 256);
   };
   auto mfma_step = [&](const Frags& fr) {
 #pragma unroll
     for (int s = 0; s < kNS; ++s) {
       const v4i a = fr.pf[Prog::sa[s]];
-      const v2i ng = fr.nf[Prog::sn[s]];
-      const v4i q = {a.z, a.w, ng.x, ng.y};
+      const v4i q = {a.z, a.w, (int)((uint32_t)a.x ^ 0x0F0F0F0Fu),
+                     (int)((uint32_t)a.y ^ 0x0F0F0F0Fu)};
       const v4i b = fr.pf[Prog::sb[s]];
       acc_re[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc_re[s], 0, 0, 0);
       acc_im[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(q, b, acc_im[s], 0, 0, 0);
@@ -370,18 +347,17 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
 
 // The 8 waves of a workgroup each run their share of the triangle.
 __device__ __forceinline__ void tri_channel(const TriParams& p, int ch, int sb, int se,
-                                            uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
-                                            uint8_t* dec_n) {
+                                            uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int simd = wave & 3;
   if (wave < 4) {
-    tri_run<ProgA>(p, ch, simd, sb, se, raw0, raw1, dec_p, dec_n);
+    tri_run<ProgA>(p, ch, simd, sb, se, raw0, raw1, dec_p);
   } else {
     switch (simd) {
-      case 0: tri_run<ProgB<0>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
-      case 1: tri_run<ProgB<1>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
-      case 2: tri_run<ProgB<2>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
-      default: tri_run<ProgB<3>>(p, ch, 0, sb, se, raw0, raw1, dec_p, dec_n); break;
+      case 0: tri_run<ProgB<0>>(p, ch, 0, sb, se, raw0, raw1, dec_p); break;
+      case 1: tri_run<ProgB<1>>(p, ch, 0, sb, se, raw0, raw1, dec_p); break;
+      case 2: tri_run<ProgB<2>>(p, ch, 0, sb, se, raw0, raw1, dec_p); break;
+      default: tri_run<ProgB<3>>(p, ch, 0, sb, se, raw0, raw1, dec_p); break;
     }
   }
 }
@@ -392,7 +368,6 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_kernel(TriParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t raw0[kRawBytes];
   __shared__ __attribute__((aligned(16))) uint8_t raw1[kRawBytes];
   __shared__ __attribute__((aligned(16))) uint8_t dec_p[kGroups * kPGroup];  // 64 KiB
-  __shared__ __attribute__((aligned(16))) uint8_t dec_n[kGroups * kNGroup];  // 32 KiB
   // Two waves per SIMD: 256 registers per wave. The accumulators (up to 160)
   // stay in ordinary VGPRs; the compiler's default split when AGPRs are in
   // use (128 + 128) could not hold them.
@@ -402,7 +377,7 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_kernel(TriParams p) {
   const int sb = part * p.stages_per_split;
   const int se = min(sb + p.stages_per_split, p.total_stages);
   if (sb >= se) return;
-  tri_channel(p, ch, sb, se, raw0, raw1, dec_p, dec_n);
+  tri_channel(p, ch, sb, se, raw0, raw1, dec_p);
 }
 
 // Persistent workgroups over a queue of (job, channel, stage range) items of
@@ -424,7 +399,7 @@ struct QueueCursor {
 template <class Prog>
 __device__ __forceinline__ void tri_queue_loop(uint8_t* ws, int hdr_offset, int base,
                                                uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
-                                               uint8_t* dec_n, QueueCursor* qc) {
+                                               QueueCursor* qc) {
   if (threadIdx.x == 0) {
     qc->part = blockIdx.x % kQueueParts;
     qc->tried = 0;
@@ -470,7 +445,7 @@ __device__ __forceinline__ void tri_queue_loop(uint8_t* ws, int hdr_offset, int 
     p.total_stages = J.total_stages;
     p.accumulate = J.accumulate;
     p.atomic_out = J.atomic_out;
-    tri_run<Prog>(p, q.ch, base, q.stage_begin, q.stage_end, raw0, raw1, dec_p, dec_n);
+    tri_run<Prog>(p, q.ch, base, q.stage_begin, q.stage_end, raw0, raw1, dec_p);
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -490,18 +465,17 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_queue_kernel(uint8_t* w
   __shared__ __attribute__((aligned(16))) uint8_t raw0[kRawBytes];
   __shared__ __attribute__((aligned(16))) uint8_t raw1[kRawBytes];
   __shared__ __attribute__((aligned(16))) uint8_t dec_p[kGroups * kPGroup];
-  __shared__ __attribute__((aligned(16))) uint8_t dec_n[kGroups * kNGroup];
   __shared__ QueueCursor qc;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int simd = wave & 3;
   if (wave < 4) {
-    tri_queue_loop<ProgA>(ws, hdr_offset, simd, raw0, raw1, dec_p, dec_n, &qc);
+    tri_queue_loop<ProgA>(ws, hdr_offset, simd, raw0, raw1, dec_p, &qc);
   } else {
     switch (simd) {
-      case 0: tri_queue_loop<ProgB<0>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &qc); break;
-      case 1: tri_queue_loop<ProgB<1>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &qc); break;
-      case 2: tri_queue_loop<ProgB<2>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &qc); break;
-      default: tri_queue_loop<ProgB<3>>(ws, hdr_offset, 0, raw0, raw1, dec_p, dec_n, &qc); break;
+      case 0: tri_queue_loop<ProgB<0>>(ws, hdr_offset, 0, raw0, raw1, dec_p, &qc); break;
+      case 1: tri_queue_loop<ProgB<1>>(ws, hdr_offset, 0, raw0, raw1, dec_p, &qc); break;
+      case 2: tri_queue_loop<ProgB<2>>(ws, hdr_offset, 0, raw0, raw1, dec_p, &qc); break;
+      default: tri_queue_loop<ProgB<3>>(ws, hdr_offset, 0, raw0, raw1, dec_p, &qc); break;
     }
   }
 }
