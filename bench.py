@@ -134,6 +134,30 @@ def bench_workload(w, steps: int, warmup: int):
     }
 
 
+def bench_time_major(w, steps: int, warmup: int):
+    """The same workload delivered as the paper's time-major packet stream
+    [T][F][N] (Sec. III, Fig. 2), correlated in place through strides."""
+    import torch
+
+    import paper_1503_06203_amd as xe
+    import synth
+    from paper_1503_06203_amd import metrics
+
+    dense = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, w.seeds()[0], common=w.common,
+                                     device="cuda:0")
+    view = dense.permute(1, 0, 2).contiguous().permute(1, 0, 2)
+    del dense
+    vis = xe.new_vis(w.n, w.f, device="cuda:0")
+    wall, per = time_steps(lambda: xe.correlate(view, vis), steps, warmup)
+    ops = metrics.effective_ops(w.n, w.f, w.t)
+    kern_s = sum(per) / len(per)
+    del view
+    torch.cuda.empty_cache()
+    return {"layout": "[T][F][N] read in place (sample stride F*N, channel stride N)",
+            "value": round(ops / (wall / steps) / 1e12, 3), "unit": "TOPS",
+            "ms_per_step": round(wall / steps * 1e3, 5), "kernel_ms": round(kern_s * 1e3, 5)}
+
+
 def cpu_baseline(w, budget_s: float = 15.0):
     """Time the CPU oracle on the first k channels of the workload (all N
     elements and T samples), k chosen from a one-channel calibration so the
@@ -307,6 +331,8 @@ def main():
             "kernel_source": digest,
         },
     }
+    if not args.no_secondary and w.name == "pathfinder":
+        line["time_major"] = bench_time_major(w, 20, 3)
     if not args.no_secondary and w.name != "large_n":
         lw = workloads.LARGE_N
         s = bench_workload(lw, 8, 2)

@@ -101,6 +101,21 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
                                    void* hip_stream);
 
 /*
+ * Correlation of a strided input, as for xeng_correlate otherwise. Element e
+ * of channel c at sample s is the byte d_in[s * sample_stride +
+ * c * channel_stride + e]; elements of one sample are contiguous. The dense
+ * layout is sample_stride = n, channel_stride = t * n; the time-major packet
+ * stream of Sec. III (Fig. 2: samples, then channels, then elements) is
+ * sample_stride = f * n, channel_stride = n, read in place with no transpose.
+ * Needs n % 4 == 0, a 4-byte aligned d_in, both strides multiples of 4,
+ * sample_stride >= n and sample_stride <= (2^31 - n) / 32; the overlap check
+ * uses the strided extent. Errors as for xeng_correlate.
+ */
+xeng_status xeng_correlate_strided(const uint8_t* d_in, int64_t sample_stride,
+                                   int64_t channel_stride, int32_t* d_vis, int n, int f, int t,
+                                   int64_t t_prev, int accumulate, void* hip_stream);
+
+/*
  * The variant and time split xeng_correlate would use for a job of this shape
  * (host only, no device work). input_aligned: the input pointer is 4-byte
  * aligned. Kernels: tri256 (n <= 256, n % 4 == 0, aligned input: one workgroup

@@ -48,26 +48,43 @@ def _check_tensors(x, vis):
         raise TypeError("vis must be an int32 tensor [F][N(N+1)/2][2]")
     if not (x.is_cuda and vis.is_cuda):
         raise TypeError("x and vis must be GPU tensors (the library has no CPU path)")
-    if not x.is_contiguous() or not vis.is_contiguous():
-        raise TypeError("x and vis must be contiguous")
+    if not vis.is_contiguous():
+        raise TypeError("vis must be contiguous")
+    if x.numel() and x.stride(2) != 1:
+        raise TypeError("x: the elements of one sample must be contiguous (stride 1)")
     f, t, n = x.shape
     if vis.numel() != 2 * f * vis_entries(n):
         raise ValueError("vis must hold F*N(N+1)/2 (re, im) pairs")
     return f, t, n
 
 
+def _dense(x):
+    f, t, n = x.shape
+    return x.is_contiguous() or (x.stride(1) == n and x.stride(0) == t * n) or x.numel() == 0
+
+
 def correlate(x, vis, t_prev: int = 0, accumulate: bool = False, stream=None):
-    """Correlate x into vis on the GPU (enqueued on ``stream``, default current)."""
+    """Correlate x into vis on the GPU (enqueued on ``stream``, default current).
+
+    x may be any [F][T][N] view whose elements are contiguous, e.g. a time-major
+    stream [T][F][N] seen as ``stream.permute(1, 0, 2)``: it is read in place."""
     f, t, n = _check_tensors(x, vis)
-    check(lib().xeng_correlate(x.data_ptr() if t else None, vis.data_ptr(), n, f, t, int(t_prev),
-                               int(bool(accumulate)), _stream_ptr(stream)))
+    if _dense(x):
+        check(lib().xeng_correlate(x.data_ptr() if t else None, vis.data_ptr(), n, f, t,
+                                   int(t_prev), int(bool(accumulate)), _stream_ptr(stream)))
+    else:
+        check(lib().xeng_correlate_strided(x.data_ptr(), int(x.stride(1)), int(x.stride(0)),
+                                           vis.data_ptr(), n, f, t, int(t_prev),
+                                           int(bool(accumulate)), _stream_ptr(stream)))
     return vis
 
 
 def correlate_variant(x, vis, variant: int, split_t: int = 1, t_prev: int = 0,
                       accumulate: bool = False, stream=None):
-    """Same as correlate() with an explicit kernel variant and time split."""
+    """Same as correlate() with an explicit kernel variant and time split (dense x)."""
     f, t, n = _check_tensors(x, vis)
+    if not _dense(x):
+        raise TypeError("correlate_variant needs a dense [F][T][N] input")
     check(lib().xeng_correlate_variant(x.data_ptr() if t else None, vis.data_ptr(), n, f, t,
                                        int(t_prev), int(bool(accumulate)), int(variant),
                                        int(split_t), _stream_ptr(stream)))

@@ -23,8 +23,11 @@ int tile128_stage_samples();
 // of each channel (t = samples per channel); t_count is limited to
 // wide_max_samples_per_launch() so the scaled int32 sums cannot overflow.
 // waves = 4 (one wave of 64x128 per SIMD) or 8 (two waves of 64x64 per SIMD).
-hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
-                       int accumulate, int split, int waves, hipStream_t stream);
+// ss, cs: bytes from one sample to the next and from one channel to the next
+// (n and t * n for the dense [F][T][N] layout; multiples of 4).
+hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                       int64_t cs, int t0, int t_count, int accumulate, int split, int waves,
+                       hipStream_t stream);
 int64_t wide_max_samples_per_launch();
 int64_t wide_tiles_per_channel(int n);
 
@@ -34,8 +37,9 @@ int64_t wide_tiles_per_channel(int n);
 // unscaled, so one launch may cover any t_count. split > 1 divides the time
 // axis and combines with int32 atomic adds (the caller zero-fills vis first
 // when not accumulating).
-hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
-                      int accumulate, int split, hipStream_t stream);
+hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                      int64_t cs, int t0, int t_count, int accumulate, int split,
+                      hipStream_t stream);
 int tri_max_elements();
 int tri_stage_samples();
 
@@ -50,6 +54,7 @@ struct QueueJob {            // one correlation job (one launch window of it)
   const uint8_t* in;
   int32_t* vis;
   int n, f, t;               // elements, channels, samples per channel
+  int64_t ss, cs;            // bytes from one sample to the next, one channel to the next
   int t0, t_end;             // window of samples this job sums
   int nbr, ntiles, total_stages;
   int accumulate, atomic_out, full_panels;
@@ -101,6 +106,8 @@ __device__ inline QueueJob load_job(QueueJobC jobs, int k) {
   J.n = jobs[k].n;
   J.f = jobs[k].f;
   J.t = jobs[k].t;
+  J.ss = jobs[k].ss;
+  J.cs = jobs[k].cs;
   J.t0 = jobs[k].t0;
   J.t_end = jobs[k].t_end;
   J.nbr = jobs[k].nbr;

@@ -61,7 +61,8 @@ struct TriParams {
   const uint8_t* in;
   int32_t* vis;
   int n, f;
-  int t;                 // samples per channel (channel stride is t * n bytes)
+  int t;                 // samples per channel
+  int64_t ss, cs;        // bytes from one sample to the next, and from one channel to the next
   int t0, t_end;         // this launch sums samples [t0, t_end)
   int split;             // workgroups along time per channel
   int stages_per_split;
@@ -148,7 +149,8 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int half = lane >> 5, l32 = lane & 31;
   const int n = p.n;
-  const uint8_t* chan = p.in + (int64_t)ch * p.t * (int64_t)n;
+  const uint8_t* chan = p.in + (int64_t)ch * p.cs;
+  const int64_t ss = p.ss;
 
   // ---- loads: this wave fetches sample rows 8*wave .. 8*wave+7 of a stage; a
   // lane carries four elements. Every stage issues exactly 8 loads per wave
@@ -162,14 +164,15 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     // a sample index (< 2^25) that is uniform across the wave; saying so keeps
     // the buffer descriptor in scalar registers
     const int first = __builtin_amdgcn_readfirstlane(p.t0 + st * kStage + 8 * wave);
-    const int64_t bytes = (int64_t)(t_stop - first) * n;
+    // up to the end of the last sample row before t_stop
+    const int64_t bytes = t_stop > first ? (int64_t)(t_stop - first - 1) * ss + n : 0;
     const int records = bytes <= 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : (int)bytes);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint8_t*>(chan + (int64_t)first * n), 0, records, 0x00020000);
+        const_cast<uint8_t*>(chan + (int64_t)first * ss), 0, records, 0x00020000);
 #pragma unroll
     for (int r = 0; r < 8; ++r)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rs, (lds_void_ptr)(raw + (8 * wave + r) * kRawStride), 4, voff + (uint32_t)(r * n), 0,
+          rs, (lds_void_ptr)(raw + (8 * wave + r) * kRawStride), 4, voff + (uint32_t)(r * ss), 0,
           0, 0);
   };
 
@@ -438,6 +441,8 @@ __device__ __forceinline__ void tri_queue_loop(uint8_t* ws, int hdr_offset, int 
     p.n = J.n;
     p.f = J.f;
     p.t = J.t;
+    p.ss = J.ss;
+    p.cs = J.cs;
     p.t0 = J.t0;
     p.t_end = J.t_end;
     p.split = 1;
@@ -492,8 +497,9 @@ hipError_t launch_queue_tri(void* d_ws, int header_offset, int grid, hipStream_t
 }
 int tri_stage_samples() { return kStage; }
 
-hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
-                      int accumulate, int split, hipStream_t stream) {
+hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                      int64_t cs, int t0, int t_count, int accumulate, int split,
+                      hipStream_t stream) {
   if (n < 1 || n > kElems || n % 4 != 0) return hipErrorInvalidValue;
   if (t_count <= 0 || t0 < 0 || (int64_t)t0 + t_count > t) return hipErrorInvalidValue;
   TriParams p;
@@ -502,6 +508,8 @@ hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int 
   p.n = n;
   p.f = f;
   p.t = t;
+  p.ss = ss;
+  p.cs = cs;
   p.t0 = t0;
   p.t_end = t0 + t_count;
   p.total_stages = (t_count + kStage - 1) / kStage;

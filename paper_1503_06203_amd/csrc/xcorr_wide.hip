@@ -58,7 +58,8 @@ struct WideParams {
   const uint8_t* in;
   int32_t* vis;
   int n, f;
-  int t;                    // samples per channel (channel stride is t * n bytes)
+  int t;                    // samples per channel
+  int64_t ss, cs;           // bytes from one sample to the next, and from one channel to the next
   int t0, t_end;            // this launch sums samples [t0, t_end)
   int nbr;                  // 128-row blocks: ceil(n / 128)
   int nbc;                  // 256-column blocks: ceil(n / 256)
@@ -79,37 +80,37 @@ struct Raw {
 };
 
 __device__ inline __amdgpu_buffer_rsrc_t stage_rsrc(const uint8_t* chan, int64_t first_row,
-                                                    int64_t n) {
+                                                    int64_t ss) {
   // every valid offset used below is < 2^31; kOob is out of range
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(chan + first_row * n), 0,
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(chan + first_row * ss), 0,
                                            0x7fffffff, 0x00020000);
 }
 
 // Fetch one stage. kChecked handles the last stage of the time axis and
 // panels that run past n: rows or elements out of range become decoded zeros.
 template <bool kChecked>
-__device__ inline void load_stage(Raw& raw, const uint8_t* chan, int n, int t0, int t_end,
+__device__ inline void load_stage(Raw& raw, const uint8_t* chan, int ss, int t0, int t_end,
                                   int stage, int wave, uint32_t voff_col, uint32_t voff_row,
                                   bool col_ok, bool row_ok, int half) {
   const int64_t first = t0 + (int64_t)stage * kStage + wave * 16;   // first row of this wave's step
-  const __amdgpu_buffer_rsrc_t rs = stage_rsrc(chan, first, n);
+  const __amdgpu_buffer_rsrc_t rs = stage_rsrc(chan, first, ss);
   if (!kChecked) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) raw.col[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff_col, r * n, 0);
+    for (int r = 0; r < 16; ++r) raw.col[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff_col, r * ss, 0);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) raw.row[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff_row, r * n, 0);
+    for (int r = 0; r < 8; ++r) raw.row[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff_row, r * ss, 0);
   } else {
     const int valid = t_end - (int)first;   // rows of this step that exist
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const bool ok = col_ok && r < valid;
-      const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_col : kOob, r * n, 0);
+      const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_col : kOob, r * ss, 0);
       raw.col[r] = ok ? v : kZeroSamples;
     }
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const bool ok = row_ok && r + 8 * half < valid;
-      const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_row : kOob, r * n, 0);
+      const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_row : kOob, r * ss, 0);
       raw.row[r] = ok ? v : kZeroSamples;
     }
   }
@@ -216,14 +217,15 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int half = lane >> 5, l32 = lane & 31;
   const int n = p.n;
-  const uint8_t* chan = p.in + (int64_t)ch * p.t * (int64_t)n;
+  const uint8_t* chan = p.in + (int64_t)ch * p.cs;
+  const int ss = (int)p.ss;
 
   // ---- staging roles: column quad = lane, row quad = l32 (rows 8*half..) --------
   const int col_e = col0 + 4 * lane;
   const int row_e = row0 + 4 * l32;
   const bool col_ok = col_e < n, row_ok = row_e < n;
   const uint32_t voff_col = (uint32_t)col_e;
-  const uint32_t voff_row = (uint32_t)row_e + (uint32_t)(8 * half) * (uint32_t)n;
+  const uint32_t voff_row = (uint32_t)row_e + (uint32_t)(8 * half) * (uint32_t)ss;
   const bool panels_full = p.full_panels != 0;
 
   // LDS destinations of this lane's staged data: its 16 raw column rows
@@ -238,10 +240,10 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
   auto fetch = [&](Raw& raw, int stage) {
     const bool tail = p.t0 + (int64_t)stage * kStage + wave * 16 + 16 > p.t_end;
     if (panels_full && !tail)
-      load_stage<false>(raw, chan, n, p.t0, p.t_end, stage, wave, voff_col, voff_row, col_ok,
+      load_stage<false>(raw, chan, ss, p.t0, p.t_end, stage, wave, voff_col, voff_row, col_ok,
                         row_ok, half);
     else
-      load_stage<true>(raw, chan, n, p.t0, p.t_end, stage, wave, voff_col, voff_row, col_ok,
+      load_stage<true>(raw, chan, ss, p.t0, p.t_end, stage, wave, voff_col, voff_row, col_ok,
                        row_ok, half);
   };
 
@@ -344,10 +346,10 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
     __builtin_amdgcn_sched_barrier(0);
     load_frags(f0, base, 0);
     if (kFast)
-      load_stage<false>(ld, chan, n, p.t0, p.t_end, ld_stage, wave, voff_col, voff_row, col_ok,
+      load_stage<false>(ld, chan, ss, p.t0, p.t_end, ld_stage, wave, voff_col, voff_row, col_ok,
                         row_ok, half);
     else if (do_ld)
-      load_stage<true>(ld, chan, n, p.t0, p.t_end, ld_stage, wave, voff_col, voff_row, col_ok,
+      load_stage<true>(ld, chan, ss, p.t0, p.t_end, ld_stage, wave, voff_col, voff_row, col_ok,
                        row_ok, half);
     __builtin_amdgcn_sched_barrier(0);
     load_frags(f1, base, 1);
@@ -458,7 +460,8 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int half = lane >> 5, l32 = lane & 31;
   const int n = p.n;
-  const uint8_t* chan = p.in + (int64_t)ch * p.t * (int64_t)n;
+  const uint8_t* chan = p.in + (int64_t)ch * p.cs;
+  const int ss = (int)p.ss;
   const bool panels_full = p.full_panels != 0;
   const int ks = wave & 3;               // K step this wave stages
   const bool row_role = wave < 4;
@@ -468,7 +471,7 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
   const int row_e = row0 + 4 * l32;
   const bool col_ok = col_e < n, row_ok = row_e < n;
   const uint32_t voff_col = (uint32_t)col_e;
-  const uint32_t voff_row = (uint32_t)row_e + (uint32_t)(8 * half) * (uint32_t)n;
+  const uint32_t voff_row = (uint32_t)row_e + (uint32_t)(8 * half) * (uint32_t)ss;
   uint8_t* const col_dst0 = lds + (ks * 16) * kColRowStride + 4 * lane;
   uint8_t* const row_dst0 = lds + kColRawBytes + ((ks * 2 + half) * kRows) * 16;
 
@@ -553,16 +556,16 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
   auto fetch = [&](auto row_tag, Raw16& raw, int stage, bool checked) {
     constexpr bool kRow = decltype(row_tag)::value;
     const int64_t first = p.t0 + (int64_t)stage * kStage + ks * 16;
-    const __amdgpu_buffer_rsrc_t rs = stage_rsrc(chan, first, n);
+    const __amdgpu_buffer_rsrc_t rs = stage_rsrc(chan, first, ss);
     const int valid = p.t_end - (int)first;
     if (kRow) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         if (!checked) {
-          raw.w[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff_row, r * n, 0);
+          raw.w[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff_row, r * ss, 0);
         } else {
           const bool ok = row_ok && r + 8 * half < valid;
-          const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_row : kOob, r * n, 0);
+          const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_row : kOob, r * ss, 0);
           raw.w[r] = ok ? v : 0u;
         }
       }
@@ -570,10 +573,10 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         if (!checked) {
-          raw.w[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff_col, r * n, 0);
+          raw.w[r] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff_col, r * ss, 0);
         } else {
           const bool ok = col_ok && r < valid;
-          const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_col : kOob, r * n, 0);
+          const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, ok ? voff_col : kOob, r * ss, 0);
           raw.w[r] = ok ? v : 0u;
         }
       }
@@ -775,6 +778,8 @@ __global__ __launch_bounds__(kThreads8, 1) void xcorr_queue_kernel(uint8_t* ws, 
     p.n = J.n;
     p.f = J.f;
     p.t = J.t;
+    p.ss = J.ss;
+    p.cs = J.cs;
     p.t0 = J.t0;
     p.t_end = J.t_end;
     p.nbr = J.nbr;
@@ -823,8 +828,9 @@ hipError_t launch_queue_wide(void* d_ws, int header_offset, int grid, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int t0, int t_count,
-                       int accumulate, int split, int waves, hipStream_t stream) {
+hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                       int64_t cs, int t0, int t_count, int accumulate, int split, int waves,
+                       hipStream_t stream) {
   if (t_count <= 0 || t_count > kMaxSamplesPerLaunch || t0 < 0 || t0 + t_count > t)
     return hipErrorInvalidValue;
   WideParams p;
@@ -833,6 +839,8 @@ hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int
   p.n = n;
   p.f = f;
   p.t = t;
+  p.ss = ss;
+  p.cs = cs;
   p.t0 = t0;
   p.t_end = t0 + t_count;
   p.nbr = (n + kRows - 1) / kRows;

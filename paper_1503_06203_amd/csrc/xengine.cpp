@@ -117,7 +117,8 @@ bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
 namespace xeng {
 // Shared validation of one correlation job; fills byte counts on success.
 xeng_status check_job(const uint8_t* d_in, const int32_t* d_vis, int n, int f, int t,
-                      int64_t t_prev, int accumulate, size_t* in_bytes, size_t* vis_bytes) {
+                      int64_t t_prev, int accumulate, size_t* in_bytes, size_t* vis_bytes,
+                      int64_t ss, int64_t cs) {
   if (n < 1 || f < 1 || t < 0)
     return fail(XENG_EINVAL, "need n >= 1, f >= 1, t >= 0 (got n=%d f=%d t=%d)", n, f, t);
   if (accumulate != 0 && accumulate != 1)
@@ -128,7 +129,11 @@ xeng_status check_job(const uint8_t* d_in, const int32_t* d_vis, int n, int f, i
   if (t_prev + (int64_t)t > XENG_MAX_SAMPLES)
     return fail(XENG_ERANGE, "t_prev + t = %lld exceeds %lld samples: int32 sums could overflow",
                 (long long)(t_prev + t), (long long)XENG_MAX_SAMPLES);
-  const unsigned __int128 ib = (unsigned __int128)f * (unsigned)t * (unsigned)n;
+  // bytes the input spans: dense [F][T][N], or the strided extent
+  unsigned __int128 ib = (unsigned __int128)f * (unsigned)t * (unsigned)n;
+  if (ss > 0 && t > 0)
+    ib = (unsigned __int128)(t - 1) * (uint64_t)ss + (unsigned __int128)(f - 1) * (uint64_t)cs +
+         (unsigned)n;
   const unsigned __int128 entries = (unsigned __int128)n * (n + 1) / 2;
   const unsigned __int128 vb = entries * (unsigned)f * 8u;
   if (ib > ((unsigned __int128)1 << 62) || vb > ((unsigned __int128)1 << 62))
@@ -169,11 +174,28 @@ const char* xeng_variant_name(int variant) {
   return (variant >= 0 && variant < kVariantCount) ? kVariants[variant].name : nullptr;
 }
 
-xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
-                                   int64_t t_prev, int accumulate, int variant, int split_t,
-                                   void* hip_stream) {
+namespace {
+
+// Shared by the dense and strided entry points. ss, cs: bytes from one sample
+// to the next and from one channel to the next (dense: n and t * n).
+xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t, int64_t ss,
+                           int64_t cs, int64_t t_prev, int accumulate, int variant, int split_t,
+                           void* hip_stream) {
+  const bool dense = ss == (int64_t)n && cs == (int64_t)t * n;
+  if (!dense) {
+    if (ss < n || cs < 0 || ss % 4 != 0 || cs % 4 != 0 || n % 4 != 0 ||
+        (uintptr_t)d_in % 4 != 0)
+      return fail(XENG_EINVAL,
+                  "strided input needs n %% 4 == 0, a 4-byte aligned base and strides that are "
+                  "multiples of 4 with sample stride >= n (got n=%d, strides %lld, %lld)",
+                  n, (long long)ss, (long long)cs);
+    if (ss > (((int64_t)1 << 31) - n) / 32)
+      return fail(XENG_EINVAL, "sample stride %lld too large (limit %lld bytes)", (long long)ss,
+                  (long long)((((int64_t)1 << 31) - n) / 32));
+  }
   size_t in_bytes = 0, vis_bytes = 0;
-  xeng_status st = check_job(d_in, d_vis, n, f, t, t_prev, accumulate, &in_bytes, &vis_bytes);
+  xeng_status st = check_job(d_in, d_vis, n, f, t, t_prev, accumulate, &in_bytes, &vis_bytes,
+                             dense ? 0 : ss, dense ? 0 : cs);
   if (st != XENG_OK) return st;
   if (variant < -1 || variant >= kVariantCount)
     return fail(XENG_ENOTFOUND, "unknown kernel variant %d", variant);
@@ -188,6 +210,9 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
   const bool aligned = (n % 4 == 0) && ((uintptr_t)d_in % 4 == 0);
   const bool tri_ok = aligned && n <= xeng::tri_max_elements();
   if (variant == -1) variant = default_variant(n, aligned);
+  if (!dense && variant == kVariantTile128)
+    return fail(XENG_EINVAL, "variant %s reads the dense [F][T][N] layout only",
+                kVariants[variant].name);
   const bool wide = variant == kVariantWide || variant == kVariantWide8;
   if (wide && !aligned)
     return fail(XENG_EINVAL, "variant %s needs n %% 4 == 0 and a 4-byte aligned input",
@@ -208,7 +233,7 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
   }
   hipError_t e = hipSuccess;
   if (variant == kVariantTri) {
-    e = xeng::launch_tri(d_in, d_vis, n, f, t, 0, t, accumulate, split, stream);
+    e = xeng::launch_tri(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
   } else if (wide) {
     // one launch per window of at most wide_max_samples_per_launch() samples;
     // windows after the first add to what the earlier ones wrote
@@ -216,7 +241,7 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
     for (int64_t t0 = 0; t0 < t && e == hipSuccess; t0 += win) {
       const int cnt = (int)std::min<int64_t>(win, t - t0);
       const int acc = (t0 == 0) ? accumulate : 1;
-      e = xeng::launch_wide(d_in, d_vis, n, f, t, (int)t0, cnt, acc, split,
+      e = xeng::launch_wide(d_in, d_vis, n, f, t, ss, cs, (int)t0, cnt, acc, split,
                             variant == kVariantWide8 ? 8 : 4, stream);
     }
   } else {
@@ -224,6 +249,22 @@ xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, i
   }
   if (e != hipSuccess) return device_error(e, "correlation kernel launch");
   return XENG_OK;
+}
+
+}  // namespace
+
+xeng_status xeng_correlate_variant(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
+                                   int64_t t_prev, int accumulate, int variant, int split_t,
+                                   void* hip_stream) {
+  return correlate_impl(d_in, d_vis, n, f, t, n, (int64_t)t * n, t_prev, accumulate, variant,
+                        split_t, hip_stream);
+}
+
+xeng_status xeng_correlate_strided(const uint8_t* d_in, int64_t sample_stride,
+                                   int64_t channel_stride, int32_t* d_vis, int n, int f, int t,
+                                   int64_t t_prev, int accumulate, void* hip_stream) {
+  return correlate_impl(d_in, d_vis, n, f, t, sample_stride, channel_stride, t_prev, accumulate,
+                        -1, 0, hip_stream);
 }
 
 xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* variant,

@@ -15,8 +15,11 @@ xeng_status fail(xeng_status st, const char* fmt, ...) __attribute__((format(pri
 // XENG_EDEVICE with the HIP error string.
 xeng_status device_error(hipError_t err, const char* what);
 // Validate one correlation job; fills its input and output byte counts.
+// ss, cs > 0: strided input (bytes between samples, between channels); the
+// overlap check then uses the strided extent. 0: dense [F][T][N].
 xeng_status check_job(const uint8_t* d_in, const int32_t* d_vis, int n, int f, int t,
-                      int64_t t_prev, int accumulate, size_t* in_bytes, size_t* vis_bytes);
+                      int64_t t_prev, int accumulate, size_t* in_bytes, size_t* vis_bytes,
+                      int64_t ss = 0, int64_t cs = 0);
 // Compute units of the current device (256 if the query fails).
 int device_cu_count();
 // Time split: `units` workgroups per split step (channels, or tiles of all

@@ -90,6 +90,8 @@ std::vector<QueueJob> job_table(xeng_plan* pl) {
     J.n = job.n;
     J.f = job.f;
     J.t = job.t;
+    J.ss = job.n;
+    J.cs = (int64_t)job.t * job.n;
     J.t0 = win.t0;
     J.t_end = win.t_end;
     J.nbr = (job.n + 127) / 128;

@@ -142,6 +142,8 @@ bool build_image(xeng_server* s, Slot& sl, const std::vector<std::pair<int64_t, 
     q.n = J.n;
     q.f = J.f;
     q.t = fr.t;
+    q.ss = J.n;
+    q.cs = (int64_t)fr.t * J.n;
     q.t0 = 0;
     q.t_end = fr.t;
     q.nbr = (J.n + 127) / 128;

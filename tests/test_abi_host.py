@@ -111,6 +111,20 @@ def test_choose_variant_dispatch_rule():
         xe.choose_variant(0, 1, 1)
 
 
+def test_strided_validation(lib):
+    st = lib.xeng_correlate_strided
+    # sample stride below n, or not a multiple of 4, or an unaligned base
+    assert st(FAKE_IN, 60, 64 * 10, FAKE_VIS, 64, 2, 10, 0, 0, None) == EINVAL
+    assert st(FAKE_IN, 66, 66 * 10, FAKE_VIS, 64, 2, 10, 0, 0, None) == EINVAL
+    assert st(FAKE_IN + 2, 128, 1280, FAKE_VIS, 64, 2, 10, 0, 0, None) == EINVAL
+    # a sample stride whose 32-bit buffer offsets would overflow
+    assert st(FAKE_IN, 1 << 27, 64, FAKE_VIS, 64, 2, 10, 0, 0, None) == EINVAL
+    # the strided extent reaches the output: time-major [T][F][N], vis right after
+    n, f, t = 64, 4, 100
+    assert st(FAKE_IN, f * n, n, FAKE_IN + t * f * n - 64, n, f, t, 0, 0, None) == EINVAL
+    assert b"overlap" in lib.xeng_last_error()
+
+
 def test_python_binding_errors_without_gpu():
     import torch
     import paper_1503_06203_amd as xe
