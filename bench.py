@@ -158,6 +158,32 @@ def bench_time_major(w, steps: int, warmup: int):
             "ms_per_step": round(wall / steps * 1e3, 5), "kernel_ms": round(kern_s * 1e3, 5)}
 
 
+def bench_gated(w, steps: int, warmup: int):
+    """Pulsar-style gating of the workload: two gate bins over blocks of 1024
+    samples, on-pulse (gate 0) one block in four, off-pulse (gate 1) the rest."""
+    import numpy as np
+    import torch
+
+    import paper_1503_06203_amd as xe
+    import synth
+    from paper_1503_06203_amd import metrics
+
+    block = 1024
+    x = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, w.seeds()[0], common=w.common,
+                                 device="cuda:0")
+    nb = (w.t + block - 1) // block
+    sched = np.array([0 if k % 4 == 0 else 1 for k in range(nb)], dtype=np.uint8)
+    vis = torch.zeros((2, w.f, xe.vis_entries(w.n), 2), dtype=torch.int32, device="cuda:0")
+    wall, _ = time_steps(lambda: xe.correlate_gated(x, vis, sched, block), steps, warmup)
+    ops = metrics.effective_ops(w.n, w.f, w.t)
+    del x, vis
+    torch.cuda.empty_cache()
+    return {"gates": 2, "block_samples": block, "schedule": "gate 0 one block in four, else gate 1",
+            "runs_per_step": int(np.count_nonzero(np.diff(sched)) + 1),
+            "value": round(ops / (wall / steps) / 1e12, 3), "unit": "TOPS",
+            "ms_per_step": round(wall / steps * 1e3, 5)}
+
+
 def cpu_baseline(w, budget_s: float = 15.0):
     """Time the CPU oracle on the first k channels of the workload (all N
     elements and T samples), k chosen from a one-channel calibration so the
@@ -333,6 +359,7 @@ def main():
     }
     if not args.no_secondary and w.name == "pathfinder":
         line["time_major"] = bench_time_major(w, 20, 3)
+        line["gated"] = bench_gated(w, 10, 2)
     if not args.no_secondary and w.name != "large_n":
         lw = workloads.LARGE_N
         s = bench_workload(lw, 8, 2)

@@ -116,6 +116,31 @@ xeng_status xeng_correlate_strided(const uint8_t* d_in, int64_t sample_stride,
                                    int64_t t_prev, int accumulate, void* hip_stream);
 
 /*
+ * Gated correlation: G accumulator sets, each time sample summed into the set
+ * of its gate. The time axis is cut into blocks of `block` samples (the last
+ * may be shorter); gate_of_block[k] (host array of ceil(t / block) bytes)
+ * names the gate of block k, 0 <= gate < gates, or 0xFF to leave the block out
+ * (flagged data). Each gate g gets V_g[i][j] = sum over its samples of
+ * x_i(t) * conj(x_j(t)) (Sec. II-A, Eq. 1), the same packed triangle as
+ * xeng_correlate.
+ *   d_in   device uint8_t[f][t][n] (dense layout), read only.
+ *   d_vis  device int32_t[gates][f][n(n+1)/2][2].
+ *   t_prev host int64_t[gates]: samples already summed per gate (used when
+ *          accumulate == 1, may be NULL when accumulate == 0).
+ *   accumulate 0 overwrites every gate's set (gates without samples become
+ *          zero), 1 adds to them; each gate's total must stay within
+ *          XENG_MAX_SAMPLES (XENG_ERANGE otherwise).
+ * Consecutive blocks of one gate are correlated in one launch; gates that
+ * change every few blocks cost one launch per run (each run is read in place
+ * as a strided sub-range, so n % 4 == 0 and a 4-byte aligned d_in are
+ * required). Errors as for xeng_correlate, XENG_EINVAL for gates < 1 or > 255,
+ * block < 1, or a gate index out of range.
+ */
+xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates, int n, int f,
+                                 int t, int block, const uint8_t* gate_of_block,
+                                 const int64_t* t_prev, int accumulate, void* hip_stream);
+
+/*
  * The variant and time split xeng_correlate would use for a job of this shape
  * (host only, no device work). input_aligned: the input pointer is 4-byte
  * aligned. Kernels: tri256 (n <= 256, n % 4 == 0, aligned input: one workgroup

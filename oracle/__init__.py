@@ -139,6 +139,24 @@ def offset_route(packed) -> np.ndarray:
     return out
 
 
+def correlate_gated(packed, gate_of_block, block: int, gates: int) -> np.ndarray:
+    """Gated correlation: int64 [G][F][N(N+1)/2][2], gate g summing Eq. 1 over
+    the samples whose block (of ``block`` samples, block k = samples
+    k*block .. k*block+block-1) is assigned to g; 0xFF leaves a block out.
+    Written from that definition: each gate's samples are gathered and
+    correlated with the plain oracle above."""
+    x = _as_input(packed)
+    f, t, n = x.shape
+    g = np.asarray(gate_of_block, dtype=np.int64)
+    out = np.zeros((gates, f, vis_entries(n), 2), dtype=np.int64)
+    sample_gate = np.repeat(g, block)[:t] if t else np.zeros(0, dtype=np.int64)
+    for gate in range(gates):
+        idx = np.nonzero(sample_gate == gate)[0]
+        if idx.size:
+            out[gate] = correlate(np.ascontiguousarray(x[:, idx, :]))
+    return out
+
+
 def threads() -> int:
     """OpenMP threads the oracle runs on."""
     return int(_load().xcorr_oracle_threads())

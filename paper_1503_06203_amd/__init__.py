@@ -14,7 +14,7 @@ from __future__ import annotations
 from . import metrics
 from ._lib import XengError, check, lib
 
-__all__ = ["correlate", "correlate_variant", "choose_variant", "new_vis", "vis_entries", "tri_index",
+__all__ = ["correlate", "correlate_variant", "correlate_gated", "choose_variant", "new_vis", "vis_entries", "tri_index",
            "tile_count", "variants", "XengError", "metrics", "MAX_SAMPLES", "Plan", "Server"]
 
 
@@ -88,6 +88,37 @@ def correlate_variant(x, vis, variant: int, split_t: int = 1, t_prev: int = 0,
     check(lib().xeng_correlate_variant(x.data_ptr() if t else None, vis.data_ptr(), n, f, t,
                                        int(t_prev), int(bool(accumulate)), int(variant),
                                        int(split_t), _stream_ptr(stream)))
+    return vis
+
+
+def correlate_gated(x, vis, gate_of_block, block: int, t_prev=None, accumulate: bool = False,
+                    stream=None):
+    """Gated correlation: vis is int32 [G][F][N(N+1)/2][2]; block k of ``block``
+    samples goes to gate gate_of_block[k] (0xFF leaves it out). t_prev: samples
+    already held per gate (accumulating)."""
+    import ctypes
+
+    import numpy as np
+    import torch
+    if x.dtype != torch.uint8 or x.dim() != 3 or not x.is_cuda or not x.is_contiguous():
+        raise TypeError("x must be a contiguous GPU uint8 tensor [F][T][N]")
+    if vis.dtype != torch.int32 or vis.dim() != 4 or not vis.is_cuda or not vis.is_contiguous():
+        raise TypeError("vis must be a contiguous GPU int32 tensor [G][F][N(N+1)/2][2]")
+    f, t, n = x.shape
+    gates = vis.shape[0]
+    if tuple(vis.shape[1:]) != (f, vis_entries(n), 2):
+        raise ValueError("vis must be [G][F][N(N+1)/2][2]")
+    g = np.ascontiguousarray(np.asarray(gate_of_block, dtype=np.uint8))
+    if g.size < (t + block - 1) // block:
+        raise ValueError("gate_of_block needs ceil(T / block) entries")
+    tp = None
+    if accumulate:
+        tp = np.ascontiguousarray(np.asarray(t_prev if t_prev is not None else [0] * gates,
+                                             dtype=np.int64))
+    check(lib().xeng_correlate_gated(
+        x.data_ptr() if t else None, vis.data_ptr(), int(gates), n, f, t, int(block),
+        g.ctypes.data_as(ctypes.c_void_p), tp.ctypes.data_as(ctypes.c_void_p) if tp is not None else None,
+        int(bool(accumulate)), _stream_ptr(stream)))
     return vis
 
 

@@ -58,6 +58,8 @@ SIGNATURES = {
     "xeng_choose_variant": (c_int, [c_int, c_int, c_int, c_int, c_intp, c_intp]),
     "xeng_correlate_strided": (c_int, [c_vp, c_i64, c_i64, c_vp, c_int, c_int, c_int, c_i64, c_int,
                                        c_vp]),
+    "xeng_correlate_gated": (c_int, [c_vp, c_vp, c_int, c_int, c_int, c_int, c_int, c_vp, c_vp,
+                                     c_int, c_vp]),
     "xeng_plan_create": (c_int, [ctypes.POINTER(c_vp), ctypes.POINTER(XengJob), c_int, c_cp]),
     "xeng_plan_workspace_bytes": (c_size, [c_vp]),
     "xeng_plan_items": (c_i64, [c_vp]),

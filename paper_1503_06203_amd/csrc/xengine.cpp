@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "xcorr_launch.h"
 #include "xengine_internal.h"
@@ -265,6 +266,74 @@ xeng_status xeng_correlate_strided(const uint8_t* d_in, int64_t sample_stride,
                                    int64_t t_prev, int accumulate, void* hip_stream) {
   return correlate_impl(d_in, d_vis, n, f, t, sample_stride, channel_stride, t_prev, accumulate,
                         -1, 0, hip_stream);
+}
+
+xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates, int n, int f,
+                                 int t, int block, const uint8_t* gate_of_block,
+                                 const int64_t* t_prev, int accumulate, void* hip_stream) {
+  if (gates < 1 || gates > 255) return fail(XENG_EINVAL, "gates must be in [1, 255] (got %d)", gates);
+  if (block < 1) return fail(XENG_EINVAL, "block must be >= 1 (got %d)", block);
+  if (n % 4 != 0 || (uintptr_t)d_in % 4 != 0)
+    return fail(XENG_EINVAL, "gated correlation needs n %% 4 == 0 and a 4-byte aligned input");
+  if (accumulate != 0 && accumulate != 1)
+    return fail(XENG_EINVAL, "accumulate must be 0 or 1 (got %d)", accumulate);
+  if (accumulate && t_prev == nullptr) return fail(XENG_EINVAL, "t_prev is NULL");
+  const int64_t nblocks = t > 0 ? ((int64_t)t + block - 1) / block : 0;
+  if (nblocks > 0 && gate_of_block == nullptr) return fail(XENG_EINVAL, "gate_of_block is NULL");
+  // per-gate sample counts and the range guard
+  std::vector<int64_t> count(gates, 0);
+  for (int64_t k = 0; k < nblocks; ++k) {
+    const int g = gate_of_block[k];
+    if (g == 0xFF) continue;
+    if (g >= gates)
+      return fail(XENG_EINVAL, "block %lld names gate %d of %d", (long long)k, g, gates);
+    count[g] += std::min<int64_t>(block, t - k * (int64_t)block);
+  }
+  for (int g = 0; g < gates; ++g) {
+    const int64_t prev = accumulate ? t_prev[g] : 0;
+    if (prev < 0) return fail(XENG_EINVAL, "t_prev[%d] < 0", g);
+    if (prev + count[g] > XENG_MAX_SAMPLES)
+      return fail(XENG_ERANGE, "gate %d would hold %lld samples: int32 sums could overflow", g,
+                  (long long)(prev + count[g]));
+  }
+  // validate the whole job once (shapes, pointers, overlap of input and all gate sets)
+  size_t in_bytes = 0, vis_bytes = 0;
+  xeng_status st = check_job(d_in, d_vis, n, f, t, 0, 0, &in_bytes, &vis_bytes);
+  if (st != XENG_OK) return st;
+  const int64_t set_pairs = (int64_t)(vis_bytes / 8);           // (re, im) pairs of one gate
+  if ((unsigned __int128)vis_bytes * (unsigned)gates > ((unsigned __int128)1 << 62))
+    return fail(XENG_EINVAL, "problem size overflows the address space");
+  if (t > 0) {
+    const uintptr_t a0 = (uintptr_t)d_in, b0 = (uintptr_t)d_vis;
+    const uintptr_t b1 = b0 + vis_bytes * (size_t)gates;
+    if (a0 < b1 && b0 < a0 + in_bytes) return fail(XENG_EINVAL, "d_in and d_vis overlap");
+  }
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  std::vector<int64_t> held(gates, 0);                           // samples summed in this call
+  for (int64_t k = 0; k < nblocks;) {
+    const int g = gate_of_block[k];
+    int64_t e = k + 1;
+    while (e < nblocks && gate_of_block[e] == g) ++e;
+    if (g != 0xFF) {
+      const int64_t s0 = k * (int64_t)block, s1 = std::min<int64_t>((int64_t)t, e * (int64_t)block);
+      const int first = !accumulate && held[g] == 0;
+      const int64_t prev = (accumulate ? t_prev[g] : 0) + held[g];
+      st = correlate_impl(d_in + s0 * n, d_vis + (int64_t)g * set_pairs * 2, n, f, (int)(s1 - s0),
+                          n, (int64_t)t * n, first ? 0 : prev, first ? 0 : 1, -1, 0, hip_stream);
+      if (st != XENG_OK) return st;
+      held[g] += s1 - s0;
+    }
+    k = e;
+  }
+  if (!accumulate) {
+    // gates that received no samples are zero
+    for (int g = 0; g < gates; ++g) {
+      if (held[g] != 0) continue;
+      hipError_t e = xeng::launch_fill_zero(d_vis + (int64_t)g * set_pairs * 2, set_pairs, stream);
+      if (e != hipSuccess) return device_error(e, "zero fill");
+    }
+  }
+  return XENG_OK;
 }
 
 xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* variant,

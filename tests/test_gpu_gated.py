@@ -1,0 +1,66 @@
+"""Gated correlation (one accumulator set per gate bin) against the oracle's
+per-gate sums."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+from gpu_helpers import assert_same  # noqa: E402
+
+
+def gated(x_dev, sched, block, gates, prev=None, t_prev=None):
+    import paper_1503_06203_amd as xe
+    f, t, n = x_dev.shape
+    vis = torch.zeros((gates, f, xe.vis_entries(n), 2), dtype=torch.int32, device=DEV)
+    if prev is not None:
+        vis.copy_(prev)
+    xe.correlate_gated(x_dev, vis, sched, block, t_prev=t_prev, accumulate=prev is not None)
+    torch.cuda.synchronize()
+    return vis
+
+
+@pytest.mark.parametrize("f,t,n,block,gates", [(2, 1000, 64, 64, 3), (1, 777, 256, 100, 2),
+                                               (3, 4096, 384, 512, 4), (2, 130, 8, 7, 2)])
+def test_gated_matches_oracle(f, t, n, block, gates):
+    x = synth.quantized_gaussian(f, t, n, 2.5, seed=f * 17 + t + n + block)
+    nb = (t + block - 1) // block
+    rng = np.random.default_rng(t + block)
+    sched = rng.integers(0, gates, nb).astype(np.uint8)
+    sched[rng.integers(0, nb)] = 0xFF                      # one flagged block
+    got = gated(x.to(DEV), sched, block, gates)
+    assert_same(got, oracle.correlate_gated(x.numpy(), sched, block, gates), "gated")
+
+
+def test_gated_accumulate_and_empty_gate():
+    f, t, n, block = 2, 512, 128, 64
+    x = synth.uniform_bytes(f, t, n, seed=31)
+    sched = np.array([0, 0, 1, 1, 0, 0, 1, 1], dtype=np.uint8)
+    first = gated(x.to(DEV), sched, block, 3)
+    assert not first[2].any()                               # gate 2 received nothing: zero
+    twice = gated(x.to(DEV), sched, block, 3, prev=first, t_prev=[256, 256, 0])
+    want = oracle.correlate_gated(x.numpy(), sched, block, 3)
+    assert_same(twice, 2 * want, "accumulated")
+
+
+def test_gated_errors():
+    import paper_1503_06203_amd as xe
+    x = torch.zeros((1, 100, 16), dtype=torch.uint8, device=DEV)
+    vis = torch.zeros((2, 1, xe.vis_entries(16), 2), dtype=torch.int32, device=DEV)
+    with pytest.raises(xe.XengError):
+        xe.correlate_gated(x, vis, [0, 5], 50)               # gate index out of range
+    with pytest.raises(xe.XengError):
+        xe.correlate_gated(x, vis, [0, 1], 50, t_prev=[xe.MAX_SAMPLES, 0], accumulate=True)

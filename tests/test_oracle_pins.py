@@ -190,3 +190,48 @@ def test_paper_numbers():
     acc = g["packed_16bit_accumulation"]
     assert 15 * 15 == acc["max_product"]              # encoded fields lie in [0, 15]
     assert acc["container_max"] // acc["max_product"] == acc["steps"]
+
+
+# ---- gated correlation (sum per gate bin) -------------------------------------------
+
+def test_gated_bruteforce(oracle_mod):
+    # tiny case through Python complex arithmetic: gate of each sample by block
+    n, t, block = 3, 11, 3
+    x, qr, qi = parts(1, t, n, seed=404)
+    gate_of_block = [1, 0, 0xFF, 1]            # samples 0-2 -> 1, 3-5 -> 0, 6-8 dropped, 9-10 -> 1
+    got = oracle_mod.correlate_gated(x, gate_of_block, block, 2)
+    gate_of_sample = [gate_of_block[s // block] for s in range(t)]
+    for g in range(2):
+        k = 0
+        for i in range(n):
+            for j in range(i, n):
+                v = 0j
+                for s in range(t):
+                    if gate_of_sample[s] != g:
+                        continue
+                    xi = complex(int(qr[0, s, i]), int(qi[0, s, i]))
+                    xj = complex(int(qr[0, s, j]), int(qi[0, s, j]))
+                    v += xi * xj.conjugate()
+                assert got[g, 0, k, 0] == int(v.real) and got[g, 0, k, 1] == int(v.imag), (g, i, j)
+                k += 1
+
+
+def test_gated_invariants(oracle_mod):
+    x = synth.uniform_bytes(2, 1000, 24, seed=405).numpy()
+    plain = oracle_mod.correlate(x)
+    nb = (1000 + 63) // 64
+    # one gate holding every block is the plain correlation
+    one = oracle_mod.correlate_gated(x, [0] * nb, 64, 1)
+    assert np.array_equal(one[0], plain)
+    # gates partition the samples: their sum is the plain correlation
+    rng = np.random.default_rng(3)
+    sched = rng.integers(0, 3, nb)
+    three = oracle_mod.correlate_gated(x, sched, 64, 3)
+    assert np.array_equal(three.sum(axis=0), plain)
+    # a dropped block is simply absent; an unused gate is zero
+    sched2 = sched.copy()
+    sched2[5] = 0xFF
+    dropped = oracle_mod.correlate_gated(x, sched2, 64, 4)
+    block5 = oracle_mod.correlate(np.ascontiguousarray(x[:, 320:384]))
+    assert np.array_equal(dropped[:3].sum(axis=0) + block5, plain)
+    assert not dropped[3].any()
