@@ -298,8 +298,9 @@ def main():
                          "scales the FETCH_SIZE / WRITE_SIZE hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (frequency "
-              "channels would shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU and has no multi-GPU path: frequency channels would "
+              "shard across GPUs with no exchange, each GPU running this same step on its "
+              "share of the channels", file=sys.stderr)
         sys.exit(2)
 
     import torch
