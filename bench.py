@@ -184,6 +184,39 @@ def bench_gated(w, steps: int, warmup: int):
             "ms_per_step": round(wall / steps * 1e3, 5)}
 
 
+def bench_delayed(w, steps: int, warmup: int):
+    """Delay compensation on the workload: per-element integer delays drawn
+    uniformly from [0, 64] samples (the first element takes the largest), a
+    64-sample halo in front of each channel, and for comparison the same call
+    with all delays equal (no relative shift). The effective rate counts the
+    frame's samples only."""
+    import numpy as np
+    import torch
+
+    import paper_1503_06203_amd as xe
+    import synth
+    from paper_1503_06203_amd import metrics
+
+    dmax = 64
+    x = synth.quantized_gaussian(w.f, w.t + dmax, w.n, w.sigma, w.seeds()[0], common=w.common,
+                                 device="cuda:0")
+    rng = np.random.default_rng(7)
+    delays = rng.integers(0, dmax + 1, w.n).astype(np.int32)
+    delays[0] = dmax
+    vis = xe.new_vis(w.n, w.f)
+    ops = metrics.effective_ops(w.n, w.f, w.t)
+    out = {"max_delay": dmax, "delays": "uniform integers in [0, %d]" % dmax}
+    wall, per = time_steps(lambda: xe.correlate_delayed(x, vis, delays), steps, warmup)
+    out.update({"value": round(ops / (wall / steps) / 1e12, 3), "unit": "TOPS",
+                "ms_per_step": round(wall / steps * 1e3, 5)})
+    same = np.full(w.n, dmax, dtype=np.int32)     # the same input, no relative shift
+    wall0, _ = time_steps(lambda: xe.correlate_delayed(x, vis, same), steps, warmup)
+    out["equal_delays_value"] = round(ops / (wall0 / steps) / 1e12, 3)
+    del x, vis
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, budget_s: float = 15.0):
     """Time the CPU oracle on the first k channels of the workload (all N
     elements and T samples), k chosen from a one-channel calibration so the
@@ -361,6 +394,7 @@ def main():
     if not args.no_secondary and w.name == "pathfinder":
         line["time_major"] = bench_time_major(w, 20, 3)
         line["gated"] = bench_gated(w, 10, 2)
+        line["delayed"] = bench_delayed(w, 10, 2)
     if not args.no_secondary and w.name != "large_n":
         lw = workloads.LARGE_N
         s = bench_workload(lw, 8, 2)

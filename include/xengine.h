@@ -141,6 +141,24 @@ xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates,
                                  const int64_t* t_prev, int accumulate, void* hip_stream);
 
 /*
+ * Delay compensation (Sec. IV: single elements shifted by whole time steps
+ * before correlation): an integer sample delay per element, applied while
+ * the samples are staged, so each element's stream is aligned before the
+ * products of Eq. 1 are summed:
+ *   V_ij = sum_{s<t} x_i(s - delays[i]) * conj(x_j(s - delays[j])).
+ *   d_in    device uint8_t[f][t + max_delay][n]: the first max_delay samples of
+ *           each channel are the halo (the end of the previous frame), sample
+ *           s of the frame is d_in[.][max_delay + s][.].
+ *   delays  host int32_t[n], each in [0, max_delay]; max_delay <= 65535.
+ *   d_vis, t_prev, accumulate as for xeng_correlate (t counts frame samples).
+ * Runs on the triangle kernel: n <= 256, and t % 64 == 0. Errors as for
+ * xeng_correlate; XENG_EINVAL for a delay out of range or t % 64 != 0.
+ */
+xeng_status xeng_correlate_delayed(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
+                                   const int32_t* delays, int max_delay, int64_t t_prev,
+                                   int accumulate, void* hip_stream);
+
+/*
  * The variant and time split xeng_correlate would use for a job of this shape
  * (host only, no device work). input_aligned: the input pointer is 4-byte
  * aligned. Kernels: tri256 (n <= 256, n % 4 == 0, aligned input: one workgroup

@@ -157,6 +157,21 @@ def correlate_gated(packed, gate_of_block, block: int, gates: int) -> np.ndarray
     return out
 
 
+def correlate_delayed(packed, delays) -> np.ndarray:
+    """Delay compensation (Sec. IV, elements shifted by whole time steps before
+    correlation): packed is [F][T + D][N] with D = max(delays);
+    returns the correlation of the aligned streams y_e(s) = x_e(D + s - d_e),
+    s < T, written from that definition (gather, then the plain oracle)."""
+    x = _as_input(packed)
+    f, tt, n = x.shape
+    d = np.asarray(delays, dtype=np.int64)
+    dmax = int(d.max()) if n else 0
+    t = tt - dmax
+    rows = dmax - d[None, :] + np.arange(t)[:, None]          # [T][N] input sample per (s, e)
+    y = x[:, rows, np.arange(n)[None, :]]                      # [F][T][N]
+    return correlate(np.ascontiguousarray(y))
+
+
 def threads() -> int:
     """OpenMP threads the oracle runs on."""
     return int(_load().xcorr_oracle_threads())

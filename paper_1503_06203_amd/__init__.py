@@ -14,7 +14,7 @@ from __future__ import annotations
 from . import metrics
 from ._lib import XengError, check, lib
 
-__all__ = ["correlate", "correlate_variant", "correlate_gated", "choose_variant", "new_vis", "vis_entries", "tri_index",
+__all__ = ["correlate", "correlate_variant", "correlate_gated", "correlate_delayed", "choose_variant", "new_vis", "vis_entries", "tri_index",
            "tile_count", "variants", "XengError", "metrics", "MAX_SAMPLES", "Plan", "Server"]
 
 
@@ -119,6 +119,31 @@ def correlate_gated(x, vis, gate_of_block, block: int, t_prev=None, accumulate: 
         x.data_ptr() if t else None, vis.data_ptr(), int(gates), n, f, t, int(block),
         g.ctypes.data_as(ctypes.c_void_p), tp.ctypes.data_as(ctypes.c_void_p) if tp is not None else None,
         int(bool(accumulate)), _stream_ptr(stream)))
+    return vis
+
+
+def correlate_delayed(x, vis, delays, t_prev: int = 0, accumulate: bool = False, stream=None):
+    """Delay compensation: x is uint8 [F][T + D][N] with D = max(delays) halo
+    samples first; element e's frame sample s is x[:, D + s - delays[e], e].
+    vis int32 [F][N(N+1)/2][2] as for correlate()."""
+    import ctypes
+
+    import numpy as np
+    import torch
+    if x.dtype != torch.uint8 or x.dim() != 3 or not x.is_cuda or not x.is_contiguous():
+        raise TypeError("x must be a contiguous GPU uint8 tensor [F][T + D][N]")
+    d = np.ascontiguousarray(np.asarray(delays, dtype=np.int32))
+    f, tt, n = x.shape
+    if d.shape != (n,):
+        raise ValueError("delays needs one entry per element")
+    dmax = int(d.max()) if n else 0
+    t = tt - dmax
+    if vis.dtype != torch.int32 or not vis.is_cuda or not vis.is_contiguous() or \
+            vis.numel() != 2 * f * vis_entries(n):
+        raise TypeError("vis must be a contiguous GPU int32 tensor [F][N(N+1)/2][2]")
+    check(lib().xeng_correlate_delayed(x.data_ptr(), vis.data_ptr(), n, f, t,
+                                       d.ctypes.data_as(ctypes.c_void_p), dmax, int(t_prev),
+                                       int(bool(accumulate)), _stream_ptr(stream)))
     return vis
 
 

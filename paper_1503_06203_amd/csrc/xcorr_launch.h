@@ -40,6 +40,13 @@ int64_t wide_tiles_per_channel(int n);
 hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
                       int64_t cs, int t0, int t_count, int accumulate, int split,
                       hipStream_t stream);
+// Delay compensation on the triangle kernel: in is uint8[f][t + max_delay][n]
+// (max_delay halo samples first); output sample s of element e is input
+// sample s + max_delay - delays[e] (host array of n values in [0, max_delay]).
+// Needs n <= tri_max_elements(), t % tri_stage_samples() == 0, t > 0.
+hipError_t launch_tri_delayed(const uint8_t* in, int32_t* vis, int n, int f, int t,
+                              const int32_t* delays, int max_delay, int accumulate, int split,
+                              hipStream_t stream);
 int tri_max_elements();
 int tri_stage_samples();
 

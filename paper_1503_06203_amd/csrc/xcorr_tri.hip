@@ -55,6 +55,18 @@ constexpr int kRawBytes = kStage * kRawStride;  // 18 KiB per raw buffer
 constexpr int kPBuf = kElems * 16;              // P slabs of one 8-sample group, one buffer
 constexpr int kPGroup = 2 * kPBuf;              // a group's slabs in both buffers
 constexpr int kGroups = kStage / 8;             // 8-sample groups per stage (= waves)
+// delay compensation: a 256-byte slot per (element group, row) and wave, one
+// LDS array per element group
+constexpr int kGathSlot = 64 * 4;
+constexpr int kGathWave = 8 * kGathSlot;
+constexpr int kGathGroup = 8 * kGathWave;           // 16 KiB per element group
+// after the stage loop the corrections reuse two groups: the per-wave partial
+// field sums (2 x 8 waves x 256 words) and the three correction rows
+static_assert(kGathGroup >= 2 * 8 * kElems * 4 && kGathGroup >= 3 * kElems * 4,
+              "the corrections fit the gather slots");
+struct GathSlots {
+  uint8_t* g[4];
+};
 constexpr uint32_t kOob = 0x80000000u;          // buffer offset past every record: load returns 0
 
 struct TriParams {
@@ -69,6 +81,14 @@ struct TriParams {
   int total_stages;
   int accumulate;
   int atomic_out;
+};
+
+// Per-element sample delays (delay compensation): element e at output sample t
+// reads input sample t + max_delay - delay[e]; the input holds max_delay halo
+// samples before the first output sample.
+struct TriDelays {
+  int max_delay;
+  uint16_t delay[kElems];
 };
 
 // ---- block programs ---------------------------------------------------------------
@@ -134,16 +154,18 @@ __device__ inline void lds_barrier() {
 // The empty asm statements keep memory operations from moving across the wait.
 template <int kLeft>
 __device__ inline void vm_wait() {
-  static_assert(kLeft >= 0 && kLeft < 16, "vmcnt field");
+  static_assert(kLeft >= 0 && kLeft < 64, "vmcnt field");
   asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_waitcnt(0x0F70 | kLeft);  // vmcnt(kLeft); lgkmcnt, expcnt at maximum
+  // vmcnt(kLeft) (bits 3:0 and 15:14); lgkmcnt and expcnt at their maximum
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (kLeft & 15) | ((kLeft >> 4) << 14));
   asm volatile("" ::: "memory");
 }
 
 
-template <class Prog>
+template <class Prog, bool kDelay = false>
 __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, int sb, int se,
-                                        uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p) {
+                                        uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
+                                        const TriDelays* dl = nullptr, GathSlots gs = {}) {
   constexpr int kNP = Prog::kNP, kNS = Prog::kNS;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -174,6 +196,48 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
           rs, (lds_void_ptr)(raw + (8 * wave + r) * kRawStride), 4, voff + (uint32_t)(r * ss), 0,
           0, 0);
+  };
+  // Delay compensation: each lane gathers the bytes of its own elements
+  // e = 64*q + lane, row r of this wave's 8 from input row
+  // (row + max_delay - delay[e]), with one-byte loads into LDS. Such a load
+  // writes each lane's byte as a zero-extended dword at 4*lane, so every
+  // (q, r) pair has a 256-byte slot private to the wave (element group q in
+  // LDS array gs.g[q]: the compiler then tracks the loads into one group apart
+  // from reads of another), and the lane reads its 8 dwords of group q back and
+  // packs their low bytes into the two words a transposing read yields in the
+  // dense form. Stages inside [sb, se) are full (the caller guarantees
+  // t % 64 == 0); for stages past se every lane uses an offset beyond every
+  // record, so the loads write zero bytes, which add nothing.
+  uint32_t voff_d[4];
+  if (kDelay) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = 64 * q + lane;
+      voff_d[q] = e < n ? (uint32_t)((dl->max_delay - (int)dl->delay[e]) * ss + e) : kOob;
+    }
+  }
+
+  // the 8 loads of element group q of stage st
+  auto gather_q = [&](int st, int q) {
+    const bool in_range = st < se;
+    const int first = __builtin_amdgcn_readfirstlane(p.t0 + (in_range ? st : sb) * kStage + 8 * wave);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t*>(chan + (int64_t)first * ss), 0, 0x7fffffff, 0x00020000);
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rs, (lds_void_ptr)(gs.g[q] + wave * kGathWave + r * kGathSlot), 1,
+          in_range ? voff_d[q] : kOob,
+          (int)(r * ss), 0, 0);
+  };
+  auto gather_read = [&](int q) {
+    uint32_t d[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      d[r] = *reinterpret_cast<const uint32_t*>(gs.g[q] + wave * kGathWave + r * kGathSlot +
+                                                4 * lane);
+    return v2i{(int)(d[0] | (d[1] << 8) | (d[2] << 16) | (d[3] << 24)),
+               (int)(d[4] | (d[5] << 8) | (d[6] << 16) | (d[7] << 24))};
   };
 
   // ---- decode: ds_read_b64_tr_b8 over the wave's 8 rows. In each 16-lane
@@ -256,21 +320,62 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     }
     lds_barrier();
   };
-
-  // ---- prologue: fetch sb and sb+1, decode sb ------------------------------------
-  fetch(raw0, sb);
-  fetch(raw1, sb + 1);
-  vm_wait<8>();
+  // The delayed form: at step ks the wave reads its bytes of element group ks
+  // of st+1 (loaded one stage earlier), decodes them and then reuses their
+  // slots for the loads of group ks of st+2. Between issuing the loads of a
+  // group and reading it back, three groups (24 loads) are issued: the wait
+  // count is the same at every step.
+  auto body_delayed = [&](auto par, int st) {
+    constexpr int kPar = decltype(par)::value;
+    Frags fr[2];
+    load_frags(fr[0], kPar, 0);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) decode(tr_read(raw0, i), 0, i);
-  lds_barrier();
+    for (int ks = 0; ks < 4; ++ks) {
+      vm_wait<24>();
+      const v2i w = gather_read(ks);
+      if (ks < 3) load_frags(fr[(ks + 1) & 1], kPar, ks + 1);
+      decode(w, kPar ^ 1, ks);
+      // the reads of the slots returned (decode used them): they may be refilled
+      __builtin_amdgcn_sched_barrier(0);
+      gather_q(st + 2, ks);
+      mfma_step(fr[ks & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    lds_barrier();
+  };
 
-  int st = sb;
-  for (; st + 1 < se; st += 2) {
-    body(std::integral_constant<int, 0>{}, st);
-    body(std::integral_constant<int, 1>{}, st + 1);
+  if (!kDelay) {
+    // ---- prologue: fetch sb and sb+1, decode sb ----------------------------------
+    fetch(raw0, sb);
+    fetch(raw1, sb + 1);
+    vm_wait<8>();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) decode(tr_read(raw0, i), 0, i);
+    lds_barrier();
+
+    int st = sb;
+    for (; st + 1 < se; st += 2) {
+      body(std::integral_constant<int, 0>{}, st);
+      body(std::integral_constant<int, 1>{}, st + 1);
+    }
+    if (st < se) body(std::integral_constant<int, 0>{}, st);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gather_q(sb, q);
+    vm_wait<0>();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) decode(gather_read(q), 0, q);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gather_q(sb + 1, q);
+    lds_barrier();
+    int st = sb;
+    for (; st + 1 < se; st += 2) {
+      body_delayed(std::integral_constant<int, 0>{}, st);
+      body_delayed(std::integral_constant<int, 1>{}, st + 1);
+    }
+    if (st < se) body_delayed(std::integral_constant<int, 0>{}, st);
   }
-  if (st < se) body(std::integral_constant<int, 0>{}, st);
   // loads issued for the two stages past se may still be writing LDS: let
   // them land (in every wave) before the raw buffers are reused below and
   // before the workgroup moves on or ends and releases its LDS
@@ -363,6 +468,44 @@ __device__ __forceinline__ void tri_channel(const TriParams& p, int ch, int sb, 
       default: tri_run<ProgB<3>>(p, ch, 0, sb, se, raw0, raw1, dec_p); break;
     }
   }
+}
+
+template <bool kDelay>
+__device__ __forceinline__ void tri_channel_t(const TriParams& p, int ch, int sb, int se,
+                                              uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
+                                              const TriDelays* dl, GathSlots gs) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int simd = wave & 3;
+  if (wave < 4) {
+    tri_run<ProgA, kDelay>(p, ch, simd, sb, se, raw0, raw1, dec_p, dl, gs);
+  } else {
+    switch (simd) {
+      case 0: tri_run<ProgB<0>, kDelay>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
+      case 1: tri_run<ProgB<1>, kDelay>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
+      case 2: tri_run<ProgB<2>, kDelay>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
+      default: tri_run<ProgB<3>, kDelay>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
+    }
+  }
+}
+
+// Delay compensation (per-element integer sample delays applied while
+// staging); the input holds max_delay halo samples before the frame.
+__global__ __launch_bounds__(kThreads, 1) void xcorr_tri_delay_kernel(TriParams p, TriDelays d) {
+  // the gather slots; after the stage loop the raw buffers of the corrections
+  // live in the same memory
+  __shared__ __attribute__((aligned(16))) uint8_t gath0[kGathGroup];
+  __shared__ __attribute__((aligned(16))) uint8_t gath1[kGathGroup];
+  __shared__ __attribute__((aligned(16))) uint8_t gath2[kGathGroup];
+  __shared__ __attribute__((aligned(16))) uint8_t gath3[kGathGroup];
+  __shared__ __attribute__((aligned(16))) uint8_t dec_p[kGroups * kPGroup];
+  // partial sums of the corrections (16 KiB) and the corrections (3 KiB)
+  uint8_t* const raw0 = gath0;
+  uint8_t* const raw1 = gath1;
+  const int ch = blockIdx.x, part = blockIdx.y;
+  const int sb = part * p.stages_per_split;
+  const int se = min(sb + p.stages_per_split, p.total_stages);
+  if (sb >= se) return;
+  tri_channel_t<true>(p, ch, sb, se, raw0, raw1, dec_p, &d, GathSlots{{gath0, gath1, gath2, gath3}});
 }
 
 __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_kernel(TriParams p) {
@@ -488,6 +631,40 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_queue_kernel(uint8_t* w
 }  // namespace
 
 int tri_max_elements() { return kElems; }
+
+hipError_t launch_tri_delayed(const uint8_t* in, int32_t* vis, int n, int f, int t,
+                              const int32_t* delays, int max_delay, int accumulate, int split,
+                              hipStream_t stream) {
+  if (n < 1 || n > kElems || t < kStage || t % kStage != 0) return hipErrorInvalidValue;
+  if (max_delay < 0 || max_delay > 65535) return hipErrorInvalidValue;
+  TriDelays d;
+  d.max_delay = max_delay;
+  for (int e = 0; e < kElems; ++e) {
+    const int v = e < n ? delays[e] : 0;
+    if (v < 0 || v > max_delay) return hipErrorInvalidValue;
+    d.delay[e] = (uint16_t)v;
+  }
+  TriParams p;
+  p.in = in;
+  p.vis = vis;
+  p.n = n;
+  p.f = f;
+  p.t = t + max_delay;
+  p.ss = n;
+  p.cs = (int64_t)(t + max_delay) * n;
+  p.t0 = 0;
+  p.t_end = t;
+  p.total_stages = t / kStage;
+  if (split < 1) split = 1;
+  if (split > p.total_stages) split = p.total_stages;
+  p.split = split;
+  p.stages_per_split = (p.total_stages + split - 1) / split;
+  p.accumulate = accumulate;
+  p.atomic_out = split > 1;
+  if (f <= 0 || split > 65535) return hipErrorInvalidConfiguration;
+  xcorr_tri_delay_kernel<<<dim3((unsigned)f, (unsigned)split), dim3(kThreads), 0, stream>>>(p, d);
+  return hipGetLastError();
+}
 
 hipError_t launch_queue_tri(void* d_ws, int header_offset, int grid, hipStream_t stream) {
   if (grid <= 0) return hipErrorInvalidConfiguration;

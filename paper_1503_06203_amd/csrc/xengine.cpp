@@ -336,6 +336,47 @@ xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates,
   return XENG_OK;
 }
 
+xeng_status xeng_correlate_delayed(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
+                                   const int32_t* delays, int max_delay, int64_t t_prev,
+                                   int accumulate, void* hip_stream) {
+  if (n < 1 || n > xeng::tri_max_elements())
+    return fail(XENG_EINVAL, "delay compensation supports 1 <= n <= %d (got %d)",
+                xeng::tri_max_elements(), n);
+  if (max_delay < 0 || max_delay > 65535)
+    return fail(XENG_EINVAL, "max_delay must be in [0, 65535] (got %d)", max_delay);
+  if (t % xeng::tri_stage_samples() != 0)
+    return fail(XENG_EINVAL, "delay compensation needs t %% %d == 0 (got t=%d)",
+                xeng::tri_stage_samples(), t);
+  if (delays == nullptr) return fail(XENG_EINVAL, "delays is NULL");
+  for (int e = 0; e < n; ++e)
+    if (delays[e] < 0 || delays[e] > max_delay)
+      return fail(XENG_EINVAL, "delay of element %d is %d, outside [0, %d]", e, delays[e],
+                  max_delay);
+  // the input holds t + max_delay samples per channel
+  size_t in_bytes = 0, vis_bytes = 0;
+  xeng_status st = check_job(d_in, d_vis, n, f, t + max_delay, t_prev, accumulate, &in_bytes,
+                             &vis_bytes);
+  if (st != XENG_OK) return st;
+  if (t_prev + (int64_t)t > XENG_MAX_SAMPLES)
+    return fail(XENG_ERANGE, "t_prev + t = %lld exceeds %lld samples", (long long)(t_prev + t),
+                (long long)XENG_MAX_SAMPLES);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  const int64_t pairs = (int64_t)(vis_bytes / 8);
+  if (t == 0) {
+    if (accumulate) return XENG_OK;
+    hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
+    return e == hipSuccess ? XENG_OK : device_error(e, "zero fill");
+  }
+  const int split = xeng::tri_auto_split(f, t, xeng::device_cu_count());
+  if (split > 1 && !accumulate) {
+    hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
+    if (e != hipSuccess) return device_error(e, "zero fill");
+  }
+  hipError_t e = xeng::launch_tri_delayed(d_in, d_vis, n, f, t, delays, max_delay, accumulate,
+                                          split, stream);
+  return e == hipSuccess ? XENG_OK : device_error(e, "delay-compensated correlation launch");
+}
+
 xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* variant,
                                 int* split_t) {
   if (n < 1 || f < 1 || t < 0)

@@ -1,0 +1,84 @@
+"""Delay compensation (per-element integer sample delays applied while the
+samples are staged) against the oracle's gather-then-correlate."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+from gpu_helpers import assert_same  # noqa: E402
+
+
+def delayed(x_dev, delays, prev=None, t_prev=0):
+    import paper_1503_06203_amd as xe
+    f, _, n = x_dev.shape
+    vis = torch.zeros((f, xe.vis_entries(n), 2), dtype=torch.int32, device=DEV)
+    if prev is not None:
+        vis.copy_(prev)
+    xe.correlate_delayed(x_dev, vis, delays, t_prev=t_prev, accumulate=prev is not None)
+    torch.cuda.synchronize()
+    return vis
+
+
+@pytest.mark.parametrize("f,t,n,dmax", [(3, 1024, 256, 300), (2, 64, 5, 7), (4, 512, 130, 64),
+                                        (1, 16384, 256, 1000), (2, 2048, 96, 1)])
+def test_delayed_matches_oracle(f, t, n, dmax):
+    print("delayed f=%d t=%d n=%d dmax=%d" % (f, t, n, dmax), flush=True)
+    rng = np.random.default_rng(f + t + n + dmax)
+    delays = rng.integers(0, dmax + 1, n)
+    delays[0] = dmax
+    x = synth.quantized_gaussian(f, t + dmax, n, 2.5, seed=f * 31 + n)
+    got = delayed(x.to(DEV), delays)
+    assert_same(got, oracle.correlate_delayed(x.numpy(), delays), "delayed")
+
+
+def test_delayed_zero_equals_plain():
+    import paper_1503_06203_amd as xe
+    x = synth.uniform_bytes(3, 1024, 256, seed=41).to(DEV)
+    got = delayed(x, np.zeros(256, dtype=np.int32))
+    plain = xe.correlate(x, xe.new_vis(256, 3))
+    torch.cuda.synchronize()
+    assert torch.equal(got, plain)
+
+
+def test_delayed_largest_delay_and_accumulate():
+    f, t, n = 1, 128, 64
+    delays = np.zeros(n, dtype=np.int32)
+    delays[::7] = 65535
+    x = synth.uniform_bytes(f, t + 65535, n, seed=42)
+    first = delayed(x.to(DEV), delays)
+    want = oracle.correlate_delayed(x.numpy(), delays)
+    assert_same(first, want, "max delay")
+    twice = delayed(x.to(DEV), delays, prev=first, t_prev=t)
+    assert_same(twice, 2 * want, "accumulated")
+
+
+def test_delayed_errors():
+    import paper_1503_06203_amd as xe
+    vis = torch.zeros((1, xe.vis_entries(16), 2), dtype=torch.int32, device=DEV)
+    with pytest.raises(xe.XengError):                       # t = 100 - 4 is not a multiple of 64
+        xe.correlate_delayed(torch.zeros((1, 100, 16), dtype=torch.uint8, device=DEV), vis,
+                             [4] + [0] * 15)
+    with pytest.raises(xe.XengError):                       # negative delay
+        xe.correlate_delayed(torch.zeros((1, 64, 16), dtype=torch.uint8, device=DEV), vis,
+                             [-1] + [0] * 15)
+    big = torch.zeros((1, 64, 300), dtype=torch.uint8, device=DEV)
+    with pytest.raises(xe.XengError):                       # beyond the triangle kernel
+        xe.correlate_delayed(big, torch.zeros((1, xe.vis_entries(300), 2), dtype=torch.int32,
+                                              device=DEV), [0] * 300)
+    with pytest.raises(xe.XengError):                       # range guard
+        xe.correlate_delayed(torch.zeros((1, 64, 16), dtype=torch.uint8, device=DEV), vis,
+                             [0] * 16, t_prev=xe.MAX_SAMPLES, accumulate=True)

@@ -235,3 +235,34 @@ def test_gated_invariants(oracle_mod):
     block5 = oracle_mod.correlate(np.ascontiguousarray(x[:, 320:384]))
     assert np.array_equal(dropped[:3].sum(axis=0) + block5, plain)
     assert not dropped[3].any()
+
+
+# ---- delay compensation ---------------------------------------------------------------
+
+def test_delayed_bruteforce(oracle_mod):
+    n, t = 3, 9
+    delays = [2, 0, 1]
+    d = max(delays)
+    x, qr, qi = parts(1, t + d, n, seed=406)
+    got = oracle_mod.correlate_delayed(x, delays)
+    k = 0
+    for i in range(n):
+        for j in range(i, n):
+            v = 0j
+            for s in range(t):
+                si, sj = d + s - delays[i], d + s - delays[j]
+                xi = complex(int(qr[0, si, i]), int(qi[0, si, i]))
+                xj = complex(int(qr[0, sj, j]), int(qi[0, sj, j]))
+                v += xi * xj.conjugate()
+            assert got[0, k, 0] == int(v.real) and got[0, k, 1] == int(v.imag), (i, j)
+            k += 1
+
+
+def test_delayed_special_cases(oracle_mod):
+    x = synth.uniform_bytes(2, 300, 16, seed=407).numpy()
+    # no delays: the last T samples, correlated plainly
+    zero = oracle_mod.correlate_delayed(x[:, :, :], [0] * 16)
+    assert np.array_equal(zero, oracle_mod.correlate(x))
+    # one common delay c with max delay D = c: the first T samples
+    common = oracle_mod.correlate_delayed(x, [44] * 16)
+    assert np.array_equal(common, oracle_mod.correlate(np.ascontiguousarray(x[:, :256])))
