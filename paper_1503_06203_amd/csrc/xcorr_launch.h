@@ -47,6 +47,14 @@ hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int6
 hipError_t launch_tri_delayed(const uint8_t* in, int32_t* vis, int n, int f, int t,
                               const int32_t* delays, int max_delay, int accumulate, int split,
                               hipStream_t stream);
+// The triangle kernel on bf6 operands (exact for 4-bit values): same
+// arguments and limits as launch_tri; split must keep every part within
+// tri_bf6_min_split's bound (returns hipErrorInvalidValue otherwise).
+hipError_t launch_tri_bf6(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                          int64_t cs, int t0, int t_count, int accumulate, int split,
+                          hipStream_t stream);
+// Smallest time split that keeps every part's fp32 sums exact.
+int tri_bf6_min_split(int64_t t_count);
 int tri_max_elements();
 int tri_stage_samples();
 

@@ -93,11 +93,13 @@ const Variant kVariants[] = {
     {"wide128x256_w4_kc64_mfma32x32x32"}, // n % 4 == 0, 4-byte aligned input
     {"wide128x256_w8_kc64_mfma32x32x32"}, // n % 4 == 0, 4-byte aligned input
     {"tri256_w8_kc64_mfma32x32x32"},      // n <= 256, n % 4 == 0, 4-byte aligned input
+    {"tri256_w8_bf6_mfma32x32x64"},       // as above, on bf6 operands (exact)
 };
 constexpr int kVariantTile128 = 0;
 constexpr int kVariantWide = 1;
 constexpr int kVariantWide8 = 2;
 constexpr int kVariantTri = 3;
+constexpr int kVariantTriBf6 = 4;
 constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // The kernel xeng_correlate uses: the triangle kernel where it applies (it
@@ -220,12 +222,14 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
                 kVariants[variant].name);
   if (wide && (int64_t)n * 32 >= ((int64_t)1 << 31))
     return fail(XENG_EINVAL, "variant %s supports n < 2^26", kVariants[variant].name);
-  if (variant == kVariantTri && !tri_ok)
+  const bool tri = variant == kVariantTri || variant == kVariantTriBf6;
+  if (tri && !tri_ok)
     return fail(XENG_EINVAL, "variant %s needs n <= %d, n %% 4 == 0 and a 4-byte aligned input",
                 kVariants[variant].name, xeng::tri_max_elements());
   int split = split_t > 0 ? split_t : 1;
-  if (variant == kVariantTri && split_t == 0)
-    split = xeng::tri_auto_split(f, t, xeng::device_cu_count());
+  if (tri && split_t == 0) split = xeng::tri_auto_split(f, t, xeng::device_cu_count());
+  // the bf6 kernel's fp32 sums are exact up to a bounded number of samples per part
+  if (variant == kVariantTriBf6) split = std::max(split, xeng::tri_bf6_min_split(t));
   if (variant == kVariantWide8 && split_t == 0)
     split = xeng::wide_auto_split(n, f, t, xeng::device_cu_count());
   if (split > 1 && !accumulate) {
@@ -235,6 +239,8 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
   hipError_t e = hipSuccess;
   if (variant == kVariantTri) {
     e = xeng::launch_tri(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
+  } else if (variant == kVariantTriBf6) {
+    e = xeng::launch_tri_bf6(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
   } else if (wide) {
     // one launch per window of at most wide_max_samples_per_launch() samples;
     // windows after the first add to what the earlier ones wrote

@@ -146,13 +146,15 @@ VARIANT_SHAPES = [(1, 64, 4), (2, 97, 128), (1, 200, 256), (2, 333, 260), (1, 10
 
 
 TRI_VARIANT = 3
+TRI_BF6_VARIANT = 4
+TRI_VARIANTS = [TRI_VARIANT, TRI_BF6_VARIANT]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("f,t,n", VARIANT_SHAPES)
 def test_each_variant_matches_oracle(variant, f, t, n):
     x = synth.quantized_gaussian(f, t, n, 3.0, seed=f * 7919 + t * 31 + n)
-    if variant == TRI_VARIANT and n > 256:
+    if variant in TRI_VARIANTS and n > 256:
         import paper_1503_06203_amd as xe
         with pytest.raises(xe.XengError):
             gpu_correlate(x.to(DEV), variant=variant, split=1)
@@ -165,41 +167,46 @@ def test_each_variant_matches_oracle(variant, f, t, n):
 # where the steady loop hands over to the drain (1, 2 and 3 stages left).
 @pytest.mark.parametrize("n", [4, 8, 32, 36, 60, 64, 96, 124, 128, 132, 160, 192, 220, 224, 228,
                                252, 256])
-def test_tri_element_counts(n):
+@pytest.mark.parametrize("tv", TRI_VARIANTS)
+def test_tri_element_counts(n, tv):
     x = synth.quantized_gaussian(2, 301, n, 3.0, seed=1000 + n)
-    full_check(x, variant=TRI_VARIANT, split=1)
+    full_check(x, variant=tv, split=1)
 
 
 @pytest.mark.parametrize("t", [1, 7, 8, 9, 63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256,
                                257, 319, 320, 321, 448, 1000])
-def test_tri_sample_counts(t):
+@pytest.mark.parametrize("tv", TRI_VARIANTS)
+def test_tri_sample_counts(t, tv):
     x = synth.quantized_gaussian(1, t, 256, 2.5, seed=2000 + t)
-    full_check(x, variant=TRI_VARIANT, split=1)
+    full_check(x, variant=tv, split=1)
 
 
 @pytest.mark.parametrize("split", [2, 3, 5, 16])
 @pytest.mark.parametrize("t", [200, 1000, 4097])
-def test_tri_time_split(split, t):
+@pytest.mark.parametrize("tv", TRI_VARIANTS)
+def test_tri_time_split(split, t, tv):
     x = synth.quantized_gaussian(3, t, 192, 2.5, seed=split * 31 + t)
     xd = x.to(DEV)
     ref = gpu_correlate(xd, variant=0, split=1)
-    got = gpu_correlate(xd, variant=TRI_VARIANT, split=split)
+    got = gpu_correlate(xd, variant=tv, split=split)
     assert torch.equal(ref, got)
     assert_same(got, oracle.correlate(x.numpy()))
     prev = torch.randint(-1000, 1000, ref.shape, dtype=torch.int32, device=DEV)
-    got2 = gpu_correlate(xd, variant=TRI_VARIANT, split=split, prev=prev.clone(), t_prev=10)
+    got2 = gpu_correlate(xd, variant=tv, split=split, prev=prev.clone(), t_prev=10)
     assert torch.equal(got2, ref + prev)
 
 
-def test_tri_accumulate_and_many_channels():
+@pytest.mark.parametrize("tv", TRI_VARIANTS)
+def test_tri_accumulate_and_many_channels(tv):
     x = synth.quantized_gaussian(300, 130, 100, 2.5, seed=61)
     xd = x.to(DEV)
-    first = gpu_correlate(xd[:, :70].contiguous(), variant=TRI_VARIANT)
-    both = gpu_correlate(xd[:, 70:].contiguous(), variant=TRI_VARIANT, prev=first, t_prev=70)
+    first = gpu_correlate(xd[:, :70].contiguous(), variant=tv)
+    both = gpu_correlate(xd[:, 70:].contiguous(), variant=tv, prev=first, t_prev=70)
     assert_same(both, oracle.correlate(x.numpy()))
 
 
-def test_tri_offset_sums_wrap_exactly():
+@pytest.mark.parametrize("tv", TRI_VARIANTS)
+def test_tri_offset_sums_wrap_exactly(tv):
     # The triangle kernel multiplies the 4-bit fields (0..15) and subtracts
     # field sums afterwards. With every byte 0xFF over the longest allowed
     # integration in one workgroup, the uncorrected sums (450 per sample) wrap
@@ -207,17 +214,28 @@ def test_tri_offset_sums_wrap_exactly():
     import paper_1503_06203_amd as xe
     t = xe.MAX_SAMPLES
     x = synth.constant_bytes(1, t, 8, 0xFF, device=DEV)
-    vis = gpu_correlate(x, variant=TRI_VARIANT, split=1).cpu().numpy()
+    vis = gpu_correlate(x, variant=tv, split=1).cpu().numpy()
     assert (vis[..., 0] == 98 * t).all() and (vis[..., 1] == 0).all()
 
 
-def test_tri_constant_extremes_exercise_masking():
+@pytest.mark.parametrize("tv", TRI_VARIANTS)
+def test_tri_constant_extremes_exercise_masking(tv):
     # 0x00 decodes to (-8,-8); any padded sample read as 0x00 instead of a
     # zero sample would add 128 per entry
     for t in (1, 65, 200):
         x = synth.constant_bytes(2, t, 256, 0x00, device=DEV)
-        vis = gpu_correlate(x, variant=TRI_VARIANT).cpu().numpy()
+        vis = gpu_correlate(x, variant=tv).cpu().numpy()
         assert (vis[..., 0] == 128 * t).all() and (vis[..., 1] == 0).all()
+
+
+@pytest.mark.parametrize("t", [131008, 131072, 262144 + 64])
+def test_tri_bf6_fp32_range(t):
+    # every byte 0x00 is (-8, -8): Re grows by 128 per sample, the most any
+    # sample adds. A bf6 part sums at most 131 008 samples (fp32 exact below
+    # 2^24); longer runs must be split whatever split the caller asks for.
+    x = synth.constant_bytes(1, t, 64, 0x00, device=DEV)
+    vis = gpu_correlate(x, variant=TRI_BF6_VARIANT, split=1).cpu().numpy()
+    assert (vis[..., 0] == 128 * t).all() and (vis[..., 1] == 0).all()
 
 
 @pytest.mark.parametrize("variant", [1, 2])

@@ -41,3 +41,11 @@ def test_triangle_kernel_has_no_scratch_and_fits_lds(tmp_path):
         assert kernel_field(asm, kernel, "amdhsa_private_segment_fixed_size") == 0
     for kernel in ("xcorr_tri_kernel", "xcorr_tri_delay_kernel", "xcorr_tri_queue_kernel"):
         assert kernel_field(asm, kernel, "amdhsa_group_segment_fixed_size") <= 160 * 1024
+
+
+def test_bf6_triangle_kernel_has_no_scratch_and_fits_lds(tmp_path):
+    # spills here would also add scratch loads to the vector-memory queue the
+    # staging waits count on (correct, but each wait would then cover them too)
+    asm = device_asm("xcorr_tri_bf6.hip", tmp_path)
+    assert kernel_field(asm, "xcorr_tri_bf6_kernel", "amdhsa_private_segment_fixed_size") == 0
+    assert kernel_field(asm, "xcorr_tri_bf6_kernel", "amdhsa_group_segment_fixed_size") <= 160 * 1024
