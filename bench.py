@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_INT8_TOPS = 5000.0      # MI355X dense int8 MFMA, TOP/s
+PEAK_FP6_TFLOPS = 10100.0    # MI355X dense fp6/fp4 MFMA, TFLOP/s
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
 
 
@@ -217,6 +218,39 @@ def bench_delayed(w, steps: int, warmup: int):
     return out
 
 
+def bench_bf6(w, steps: int, warmup: int):
+    """The exact bf6 path (the triangle kernel on the f8f6f4 matrix cores,
+    variant 4) on the same workload, reported apart from the int8 metric: its
+    roofline is the fp6 peak. Also checks that its result equals the default
+    path's bit for bit."""
+    import torch
+
+    import paper_1503_06203_amd as xe
+    import synth
+    from paper_1503_06203_amd import metrics
+
+    variant = 4
+    x = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, w.seeds()[0], common=w.common,
+                                 device="cuda:0")
+    vis = xe.new_vis(w.n, w.f)
+    wall, per = time_steps(lambda: xe.correlate_variant(x, vis, variant, split_t=0), steps, warmup)
+    ref = xe.correlate(x, xe.new_vis(w.n, w.f))
+    torch.cuda.synchronize()
+    same = bool(torch.equal(ref, vis))
+    ops = metrics.effective_ops(w.n, w.f, w.t)
+    kern_s = sum(per) / len(per)
+    del x, vis, ref
+    torch.cuda.empty_cache()
+    achieved = ops / kern_s / 1e12
+    return {"variant": xe.variants()[variant], "dtype": "bf6 (E3M2), fp32 accumulate",
+            "value": round(ops / (wall / steps) / 1e12, 3), "unit": "TOPS",
+            "ms_per_step": round(wall / steps * 1e3, 5), "kernel_ms": round(kern_s * 1e3, 5),
+            "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
+                         "peak": PEAK_FP6_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(achieved / PEAK_FP6_TFLOPS, 4)},
+            "identical_to_int8_path": same}
+
+
 def cpu_baseline(w, budget_s: float = 15.0):
     """Time the CPU oracle on the first k channels of the workload (all N
     elements and T samples), k chosen from a one-channel calibration so the
@@ -395,6 +429,7 @@ def main():
         line["time_major"] = bench_time_major(w, 20, 3)
         line["gated"] = bench_gated(w, 10, 2)
         line["delayed"] = bench_delayed(w, 10, 2)
+        line["bf6"] = bench_bf6(w, 20, 3)
     if not args.no_secondary and w.name != "large_n":
         lw = workloads.LARGE_N
         s = bench_workload(lw, 8, 2)
