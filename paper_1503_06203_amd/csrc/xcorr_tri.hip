@@ -70,15 +70,33 @@ struct GathSlots {
 // samples before the first output sample.
 struct TriDelays {
   int max_delay;
+  int lo, hi;   // smallest and largest max_delay - delay[e] over the elements
   uint16_t delay[kElems];
 };
+// Delay compensation with a bounded spread (hi - lo <= kRingSpread): the
+// sample rows an output stage needs, [st*64 + lo, st*64 + 64 + hi), are loaded
+// whole (coalesced, like the dense form) into a ring of kRingRows rows in LDS,
+// and each lane gathers its elements' bytes from there. Slot k of the ring
+// holds rows congruent to k modulo kRingRows; the first kRingGuard slots are
+// also written after the last one, so the 8 consecutive rows a gather reads
+// never wrap. A row stride of 65 dwords spreads the bytes of different rows
+// over the LDS banks.
+constexpr int kRingRows = 256;
+constexpr int kRingGuard = 7;
+constexpr int kRingStride = kElems + 4;
+constexpr int kRingBytes = ((kRingRows + kRingGuard) * kRingStride + 15) / 16 * 16;
+constexpr int kRingSpread = kRingRows - 2 * kStage;   // the window and the rows loaded ahead
+static_assert(kRingBytes >= 2 * 8 * kElems * 4 + 4096, "the corrections fit the ring");
+// delay modes of the triangle kernel
+constexpr int kDense = 0, kGather = 1, kWindow = 2;
 
 
-template <class Prog, bool kDelay = false>
+template <class Prog, int kMode = kDense>
 __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, int sb, int se,
                                         uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
                                         const TriDelays* dl = nullptr, GathSlots gs = {}) {
   constexpr int kNP = Prog::kNP, kNS = Prog::kNS;
+  constexpr bool kDelay = kMode == kGather;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int half = lane >> 5, l32 = lane & 31;
@@ -152,13 +170,62 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
                (int)(d[4] | (d[5] << 8) | (d[6] << 16) | (d[7] << 24))};
   };
 
+  // Window form (kWindow): raw0 is the ring. ring_load(r0, r1) loads rows
+  // [r0, r1) of the channel, 8 per wave per round (row r0 + 8*w + r of each
+  // round of 64); the descriptor ends at the channel's last row (t rows,
+  // halo included), so rows past it read zeros.
+  auto ring_load = [&](int r0, int r1) {
+    for (int rb = r0; rb < r1; rb += kStage) {
+      const int first = __builtin_amdgcn_readfirstlane(rb + 8 * wave);
+      const int64_t bytes = (int64_t)(p.t - first) * ss;
+      const int records = bytes <= 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : (int)bytes);
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<uint8_t*>(chan + (int64_t)first * ss), 0, records, 0x00020000);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int row = first + r;
+        if (row < r1) {
+          const int slot = row & (kRingRows - 1);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_ptr)(raw0 + slot * kRingStride),
+                                                   4, voff, r * (int)ss, 0, 0);
+          if (slot < kRingGuard)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rs, (lds_void_ptr)(raw0 + (kRingRows + slot) * kRingStride), 4, voff,
+                r * (int)ss, 0, 0);
+        }
+      }
+    }
+  };
+  // the 8 bytes of element 64*q + lane at this wave's rows of stage st, packed
+  // as a transposing read would give them; ring_off[q] = max_delay - delay[e]
+  int ring_off[4];
+  if (kMode == kWindow) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = 64 * q + lane;
+      ring_off[q] = e < n ? dl->max_delay - (int)dl->delay[e] : dl->lo;
+    }
+  }
+  auto ring_gather = [&](int st, int q) {
+    const int row0 = st * kStage + 8 * wave + ring_off[q];
+    const uint8_t* const a = raw0 + (row0 & (kRingRows - 1)) * kRingStride + 64 * q + lane;
+    uint32_t d[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) d[r] = a[r * kRingStride];
+    return v2i{(int)(d[0] | (d[1] << 8) | (d[2] << 16) | (d[3] << 24)),
+               (int)(d[4] | (d[5] << 8) | (d[6] << 16) | (d[7] << 24))};
+  };
+
   // ---- decode: ds_read_b64_tr_b8 over the wave's 8 rows. In each 16-lane
   // group the even lanes name the rows of elements e0..e0+7 and the odd lanes
   // those of e0+8..e0+15; lane k of the group receives element e0+k, byte m =
   // sample m. Read i covers elements 64*i .. 64*i+63 (lane = element - 64*i).
   const int lq = lane & 15;
   const int tr_off = (8 * wave + (lq >> 1)) * kRawStride + 16 * ((lane >> 4) & 3) + 8 * (lq & 1);
-  uint8_t* const wr_p = dec_p + wave * kPGroup + lane * 16;
+  // stores into dec_p use one offset from the array (not a chain of pointer
+  // steps): the compiler then keeps their link to dec_p and does not make
+  // them wait for loads into other LDS arrays
+  const int wr_off = wave * kPGroup + lane * 16;
   auto tr_read = [&](const uint8_t* raw, int i) {
     return __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i_ptr)(raw + tr_off + 64 * i));
   };
@@ -168,14 +235,14 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     const uint32_t ra = fields_hi((uint32_t)w.x), rb = fields_hi((uint32_t)w.y);
     const uint32_t ia = fields_lo((uint32_t)w.x), ib = fields_lo((uint32_t)w.y);
     const v4i ps = {(int)ra, (int)rb, (int)ia, (int)ib};
-    *reinterpret_cast<v4i*>(wr_p + buf * kPBuf + i * 1024) = ps;
+    *reinterpret_cast<v4i*>(dec_p + (wr_off + buf * kPBuf + i * 1024)) = ps;
     // v_sad_u8 against zero adds the four bytes of a word
     sum_re[i] = __builtin_amdgcn_sad_u8(rb, 0u, __builtin_amdgcn_sad_u8(ra, 0u, sum_re[i]));
     sum_im[i] = __builtin_amdgcn_sad_u8(ib, 0u, __builtin_amdgcn_sad_u8(ia, 0u, sum_im[i]));
   };
 
   // ---- MFMA operands: lane half h reads group 2*ks + h, element 32*block + l32
-  const uint8_t* const rd_p = dec_p + half * kPGroup + (32 * base + l32) * 16;
+  const int rd_off = half * kPGroup + (32 * base + l32) * 16;
   v16i acc_re[kNS], acc_im[kNS];
 #pragma unroll
   for (int s = 0; s < kNS; ++s) {
@@ -189,8 +256,8 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   auto load_frags = [&](Frags& fr, int buf, int ks) {
 #pragma unroll
     for (int k = 0; k < kNP; ++k)
-      fr.pf[k] = *reinterpret_cast<const v4i*>(rd_p + ks * 2 * kPGroup + buf * kPBuf +
-                                               Prog::p[k] * 512);
+      fr.pf[k] = *reinterpret_cast<const v4i*>(
+          dec_p + (rd_off + ks * 2 * kPGroup + buf * kPBuf + Prog::p[k] * 512));
   };
   auto mfma_step = [&](const Frags& fr) {
 #pragma unroll
@@ -256,7 +323,51 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
     lds_barrier();
   };
 
-  if (!kDelay) {
+  // The window form: at stage st the rows of st+1 are gathered (they were
+  // loaded, and every wave waited for its loads, before the previous stage
+  // barrier), then the rows that st+2 adds to the window are requested, and
+  // every wave waits for its own requests before this stage's barrier. The
+  // ring then holds [(st+1)*64 + lo, (st+3)*64 + hi): 128 + hi - lo rows.
+  // Stages past se are gathered as zeros (their field sums must stay out).
+  auto body_window = [&](auto par, int st) {
+    constexpr int kPar = decltype(par)::value;
+    Frags fr[2];
+    load_frags(fr[0], kPar, 0);
+    v2i rawv[4];
+    const bool live = st + 1 < se;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const v2i g = ring_gather(st + 1, q);
+      rawv[q] = live ? g : v2i{0, 0};
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    ring_load((st + 2) * kStage + dl->hi, (st + 3) * kStage + dl->hi);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      if (ks < 3) load_frags(fr[(ks + 1) & 1], kPar, ks + 1);
+      decode(rawv[ks], kPar ^ 1, ks);
+      mfma_step(fr[ks & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    vm_wait<0>();
+    lds_barrier();
+  };
+
+  if (kMode == kWindow) {
+    // the rows of stages sb and sb+1: [sb*64 + lo, (sb+2)*64 + hi)
+    ring_load(sb * kStage + dl->lo, (sb + 2) * kStage + dl->hi);
+    vm_wait<0>();
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) decode(ring_gather(sb, q), 0, q);
+    lds_barrier();
+    int st = sb;
+    for (; st + 1 < se; st += 2) {
+      body_window(std::integral_constant<int, 0>{}, st);
+      body_window(std::integral_constant<int, 1>{}, st + 1);
+    }
+    if (st < se) body_window(std::integral_constant<int, 0>{}, st);
+  } else if (!kDelay) {
     // ---- prologue: fetch sb and sb+1, decode sb ----------------------------------
     fetch(raw0, sb);
     fetch(raw1, sb + 1);
@@ -328,7 +439,7 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   const int64_t entries = n64 * (n64 + 1) / 2;
   int32_t* out = p.vis + (int64_t)ch * entries * 2;
   auto store_all = [&](auto mode) {
-    constexpr int kMode = decltype(mode)::value;   // 0 store, 1 add, 2 atomic add
+    constexpr int kStore = decltype(mode)::value;   // 0 store, 1 add, 2 atomic add
 #pragma unroll
     for (int s = 0; s < kNS; ++s) {
       const int rb = base + Prog::p[Prog::sa[s]], cb = base + Prog::p[Prog::sb[s]];
@@ -344,10 +455,10 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
           const int re = (int)((uint32_t)acc_re[s][r] + re_j - (uint32_t)corr[i]);
           const int im =
               (int)((uint32_t)acc_im[s][r] + (uint32_t)corr[kElems + i] - ci_col_j);
-          if (kMode == 2) {
+          if (kStore == 2) {
             atomicAdd(o, re);
             atomicAdd(o + 1, im);
-          } else if (kMode == 1) {
+          } else if (kStore == 1) {
             const v2i old = *reinterpret_cast<const v2i*>(o);
             *reinterpret_cast<v2i*>(o) = v2i{old.x + re, old.y + im};
           } else {
@@ -382,20 +493,20 @@ __device__ __forceinline__ void tri_channel(const TriParams& p, int ch, int sb, 
   }
 }
 
-template <bool kDelay>
+template <int kMode>
 __device__ __forceinline__ void tri_channel_t(const TriParams& p, int ch, int sb, int se,
                                               uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
                                               const TriDelays* dl, GathSlots gs) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int simd = wave & 3;
   if (wave < 4) {
-    tri_run<ProgA, kDelay>(p, ch, simd, sb, se, raw0, raw1, dec_p, dl, gs);
+    tri_run<ProgA, kMode>(p, ch, simd, sb, se, raw0, raw1, dec_p, dl, gs);
   } else {
     switch (simd) {
-      case 0: tri_run<ProgB<0>, kDelay>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
-      case 1: tri_run<ProgB<1>, kDelay>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
-      case 2: tri_run<ProgB<2>, kDelay>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
-      default: tri_run<ProgB<3>, kDelay>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
+      case 0: tri_run<ProgB<0>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
+      case 1: tri_run<ProgB<1>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
+      case 2: tri_run<ProgB<2>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
+      default: tri_run<ProgB<3>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
     }
   }
 }
@@ -417,7 +528,22 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_delay_kernel(TriParams 
   const int sb = part * p.stages_per_split;
   const int se = min(sb + p.stages_per_split, p.total_stages);
   if (sb >= se) return;
-  tri_channel_t<true>(p, ch, sb, se, raw0, raw1, dec_p, &d, GathSlots{{gath0, gath1, gath2, gath3}});
+  tri_channel_t<kGather>(p, ch, sb, se, raw0, raw1, dec_p, &d,
+                         GathSlots{{gath0, gath1, gath2, gath3}});
+}
+
+// Delay compensation for delay spreads up to kRingSpread samples: the sample
+// window of each stage is loaded whole into an LDS ring and gathered there.
+__global__ __launch_bounds__(kThreads, 1) void xcorr_tri_window_kernel(TriParams p, TriDelays d) {
+  __shared__ __attribute__((aligned(16))) uint8_t ring[kRingBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t dec_p[kGroups * kPGroup];
+  const int ch = blockIdx.x, part = blockIdx.y;
+  const int sb = part * p.stages_per_split;
+  const int se = min(sb + p.stages_per_split, p.total_stages);
+  if (sb >= se) return;
+  // after the stage loop the ring holds the corrections' partial sums (raw0)
+  // and the corrections (raw1)
+  tri_channel_t<kWindow>(p, ch, sb, se, ring, ring + 2 * 8 * kElems * 4, dec_p, &d, GathSlots{});
 }
 
 __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_kernel(TriParams p) {
@@ -551,11 +677,20 @@ hipError_t launch_tri_delayed(const uint8_t* in, int32_t* vis, int n, int f, int
   if (max_delay < 0 || max_delay > 65535) return hipErrorInvalidValue;
   TriDelays d;
   d.max_delay = max_delay;
+  int dmin = max_delay, dmax = 0;
   for (int e = 0; e < kElems; ++e) {
     const int v = e < n ? delays[e] : 0;
     if (v < 0 || v > max_delay) return hipErrorInvalidValue;
     d.delay[e] = (uint16_t)v;
+    if (e < n) {
+      dmin = v < dmin ? v : dmin;
+      dmax = v > dmax ? v : dmax;
+    }
   }
+  d.lo = max_delay - dmax;
+  d.hi = max_delay - dmin;
+  // the ring loads whole rows with dword loads: n % 4 == 0
+  const bool window = d.hi - d.lo <= kRingSpread && n % 4 == 0;
   TriParams p;
   p.in = in;
   p.vis = vis;
@@ -574,7 +709,12 @@ hipError_t launch_tri_delayed(const uint8_t* in, int32_t* vis, int n, int f, int
   p.accumulate = accumulate;
   p.atomic_out = split > 1;
   if (f <= 0 || split > 65535) return hipErrorInvalidConfiguration;
-  xcorr_tri_delay_kernel<<<dim3((unsigned)f, (unsigned)split), dim3(kThreads), 0, stream>>>(p, d);
+  if (window)
+    xcorr_tri_window_kernel<<<dim3((unsigned)f, (unsigned)split), dim3(kThreads), 0, stream>>>(p,
+                                                                                            d);
+  else
+    xcorr_tri_delay_kernel<<<dim3((unsigned)f, (unsigned)split), dim3(kThreads), 0, stream>>>(p,
+                                                                                           d);
   return hipGetLastError();
 }
 

@@ -82,3 +82,38 @@ def test_delayed_errors():
     with pytest.raises(xe.XengError):                       # range guard
         xe.correlate_delayed(torch.zeros((1, 64, 16), dtype=torch.uint8, device=DEV), vis,
                              [0] * 16, t_prev=xe.MAX_SAMPLES, accumulate=True)
+
+
+# Delay spreads up to 128 samples with n % 4 == 0 take the window form (the
+# rows of a stage loaded whole into an LDS ring, gathered there); the cases
+# above with larger spreads or odd n take the per-byte gather form.
+@pytest.mark.parametrize("f,t,n,lo,hi", [(3, 1024, 256, 0, 128), (2, 640, 64, 37, 137),
+                                         (1, 16384, 256, 0, 100), (5, 192, 4, 10, 11),
+                                         (2, 4096, 132, 64, 191)])
+def test_delayed_window_form(f, t, n, lo, hi):
+    print("window f=%d t=%d n=%d delays %d..%d" % (f, t, n, lo, hi), flush=True)
+    rng = np.random.default_rng(f * 7 + n + hi)
+    delays = rng.integers(lo, hi + 1, n)
+    delays[0], delays[-1] = lo, hi
+    dmax = hi
+    x = synth.quantized_gaussian(f, t + dmax, n, 2.5, seed=f * 31 + n + 5)
+    got = delayed(x.to(DEV), delays)
+    assert_same(got, oracle.correlate_delayed(x.numpy(), delays), "window")
+
+
+def test_delayed_window_accumulate_matches_gather_form():
+    # the same delays once within the window spread and once with one more
+    # element far outside it (gather form): both equal the oracle
+    f, t, n = 2, 2048, 128
+    rng = np.random.default_rng(3)
+    near = rng.integers(0, 60, n)
+    x = synth.uniform_bytes(f, t + 400, n, seed=77)
+    xn = x[:, :t + int(near.max())].contiguous()       # [F][T + D][N], D = the largest delay
+    first = delayed(xn.to(DEV), near)
+    twice = delayed(xn.to(DEV), near, prev=first, t_prev=t)
+    want = oracle.correlate_delayed(xn.numpy(), near)
+    assert_same(twice, 2 * want, "window accumulate")
+    far = near.copy()
+    far[5] = 400
+    got = delayed(x.to(DEV), far)
+    assert_same(got, oracle.correlate_delayed(x.numpy(), far), "gather form")
