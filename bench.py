@@ -181,6 +181,7 @@ def bench_gated(w, steps: int, warmup: int):
     torch.cuda.empty_cache()
     return {"gates": 2, "block_samples": block, "schedule": "gate 0 one block in four, else gate 1",
             "runs_per_step": int(np.count_nonzero(np.diff(sched)) + 1),
+            "launches_per_step": 2 if w.n <= 256 else int(np.count_nonzero(np.diff(sched)) + 1),
             "value": round(ops / (wall / steps) / 1e12, 3), "unit": "TOPS",
             "ms_per_step": round(wall / steps * 1e3, 5)}
 

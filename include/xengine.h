@@ -138,10 +138,10 @@ xeng_status xeng_correlate_strided(const uint8_t* d_in, int64_t sample_stride,
  *   accumulate 0 overwrites every gate's set (gates without samples become
  *          zero), 1 adds to them; each gate's total must stay within
  *          XENG_MAX_SAMPLES (XENG_ERANGE otherwise).
- * Consecutive blocks of one gate are correlated in one launch; gates that
- * change every few blocks cost one launch per run (each run is read in place
- * as a strided sub-range, so n % 4 == 0 and a 4-byte aligned d_in are
- * required). Errors as for xeng_correlate, XENG_EINVAL for gates < 1 or > 255,
+ * For n <= 256 all runs of one gate (consecutive blocks of that gate) are
+ * summed in one launch per gate (up to 32 runs each); for larger n each run
+ * is one launch. Runs are read in place as sub-ranges, so n % 4 == 0 and a
+ * 4-byte aligned d_in are required. Errors as for xeng_correlate, XENG_EINVAL for gates < 1 or > 255,
  * block < 1, or a gate index out of range.
  */
 xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates, int n, int f,

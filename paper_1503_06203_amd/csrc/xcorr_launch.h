@@ -55,6 +55,13 @@ hipError_t launch_tri_bf6(const uint8_t* in, int32_t* vis, int n, int f, int t, 
                           hipStream_t stream);
 // Smallest time split that keeps every part's fp32 sums exact.
 int tri_bf6_min_split(int64_t t_count);
+// The triangle kernel over several sample segments [seg_t0[k], seg_t_end[k])
+// of each channel (host arrays, 1 <= count <= tri_max_segments()), summed
+// into one result; otherwise as launch_tri.
+hipError_t launch_tri_segments(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                               int64_t cs, const int32_t* seg_t0, const int32_t* seg_t_end,
+                               int count, int accumulate, int split, hipStream_t stream);
+int tri_max_segments();
 int tri_max_elements();
 int tri_stage_samples();
 

@@ -87,14 +87,26 @@ constexpr int kRingStride = kElems + 4;
 constexpr int kRingBytes = ((kRingRows + kRingGuard) * kRingStride + 15) / 16 * 16;
 constexpr int kRingSpread = kRingRows - 2 * kStage;   // the window and the rows loaded ahead
 static_assert(kRingBytes >= 2 * 8 * kElems * 4 + 4096, "the corrections fit the ring");
-// delay modes of the triangle kernel
-constexpr int kDense = 0, kGather = 1, kWindow = 2;
+// Sample segments (gated correlation): the workgroup sums the samples
+// [t0[k], t_end[k]) of every segment k; segment k covers the stages
+// [stage0[k], stage0[k+1]) of the stage loop, each stage 64 samples of one
+// segment (the last one of a segment may be partial).
+constexpr int kMaxSegments = 32;
+struct TriSegments {
+  int count;
+  int t0[kMaxSegments];
+  int t_end[kMaxSegments];
+  int stage0[kMaxSegments + 1];
+};
+// modes of the triangle kernel: dense, the two delay forms, sample segments
+constexpr int kDense = 0, kGather = 1, kWindow = 2, kSegments = 3;
 
 
 template <class Prog, int kMode = kDense>
 __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, int sb, int se,
                                         uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
-                                        const TriDelays* dl = nullptr, GathSlots gs = {}) {
+                                        const TriDelays* dl = nullptr, GathSlots gs = {},
+                                        const TriSegments* sg = nullptr) {
   constexpr int kNP = Prog::kNP, kNS = Prog::kNS;
   constexpr bool kDelay = kMode == kGather;
   const int tid = threadIdx.x;
@@ -112,12 +124,27 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   // use an offset beyond every record.
   const uint32_t voff = (4 * lane < n) ? 4u * (uint32_t)lane : kOob;
   const int t_stop = min(p.t_end, p.t0 + se * kStage);   // samples [t0 + sb*64, t_stop)
+  // first sample of stage st and the end of its samples; in the segment mode
+  // stages past se (loaded ahead, never multiplied) are empty
+  auto stage_span = [&](int st, int& row0, int& stop) {
+    if (kMode == kSegments) {
+      int k = 0;
+      while (k + 1 < sg->count && sg->stage0[k + 1] <= st) ++k;
+      row0 = sg->t0[k] + (st - sg->stage0[k]) * kStage;
+      stop = st < se ? sg->t_end[k] : row0;
+    } else {
+      row0 = p.t0 + st * kStage;
+      stop = t_stop;
+    }
+  };
   auto fetch = [&](uint8_t* raw, int st) {
+    int row0, stop;
+    stage_span(st, row0, stop);
     // a sample index (< 2^25) that is uniform across the wave; saying so keeps
     // the buffer descriptor in scalar registers
-    const int first = __builtin_amdgcn_readfirstlane(p.t0 + st * kStage + 8 * wave);
-    // up to the end of the last sample row before t_stop
-    const int64_t bytes = t_stop > first ? (int64_t)(t_stop - first - 1) * ss + n : 0;
+    const int first = __builtin_amdgcn_readfirstlane(row0 + 8 * wave);
+    // up to the end of the last sample row before the stop
+    const int64_t bytes = stop > first ? (int64_t)(stop - first - 1) * ss + n : 0;
     const int records = bytes <= 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : (int)bytes);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(chan + (int64_t)first * ss), 0, records, 0x00020000);
@@ -431,7 +458,17 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   }
   lds_barrier();
   // samples this workgroup summed (stages sb..se-1 within t_end)
-  const int t_sum = max(0, t_stop - (p.t0 + sb * kStage));
+  int t_sum = max(0, t_stop - (p.t0 + sb * kStage));
+  if (kMode == kSegments) {
+    // the samples of each segment that fall into stages [sb, se)
+    t_sum = 0;
+    for (int k = 0; k < sg->count; ++k) {
+      const int lo = max(sb, sg->stage0[k]), hi = min(se, sg->stage0[k + 1]);
+      if (lo < hi)
+        t_sum += min(sg->t_end[k], sg->t0[k] + (hi - sg->stage0[k]) * kStage) -
+                 (sg->t0[k] + (lo - sg->stage0[k]) * kStage);
+    }
+  }
   const uint32_t re_const = 128u * (uint32_t)t_sum;
 
   // ---- epilogue: masked writes of i <= j < n into the packed triangle ------------
@@ -496,17 +533,18 @@ __device__ __forceinline__ void tri_channel(const TriParams& p, int ch, int sb, 
 template <int kMode>
 __device__ __forceinline__ void tri_channel_t(const TriParams& p, int ch, int sb, int se,
                                               uint8_t* raw0, uint8_t* raw1, uint8_t* dec_p,
-                                              const TriDelays* dl, GathSlots gs) {
+                                              const TriDelays* dl, GathSlots gs,
+                                              const TriSegments* sg = nullptr) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int simd = wave & 3;
   if (wave < 4) {
-    tri_run<ProgA, kMode>(p, ch, simd, sb, se, raw0, raw1, dec_p, dl, gs);
+    tri_run<ProgA, kMode>(p, ch, simd, sb, se, raw0, raw1, dec_p, dl, gs, sg);
   } else {
     switch (simd) {
-      case 0: tri_run<ProgB<0>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
-      case 1: tri_run<ProgB<1>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
-      case 2: tri_run<ProgB<2>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
-      default: tri_run<ProgB<3>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs); break;
+      case 0: tri_run<ProgB<0>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs, sg); break;
+      case 1: tri_run<ProgB<1>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs, sg); break;
+      case 2: tri_run<ProgB<2>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs, sg); break;
+      default: tri_run<ProgB<3>, kMode>(p, ch, 0, sb, se, raw0, raw1, dec_p, dl, gs, sg); break;
     }
   }
 }
@@ -544,6 +582,21 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_window_kernel(TriParams
   // after the stage loop the ring holds the corrections' partial sums (raw0)
   // and the corrections (raw1)
   tri_channel_t<kWindow>(p, ch, sb, se, ring, ring + 2 * 8 * kElems * 4, dec_p, &d, GathSlots{});
+}
+
+// Several sample segments of each channel summed into one result (the runs of
+// one gate of a gated correlation): the same kernel, with the stage loop
+// running over the segments' stages.
+__global__ __launch_bounds__(kThreads, 1) void xcorr_tri_segments_kernel(TriParams p,
+                                                                         TriSegments sg) {
+  __shared__ __attribute__((aligned(16))) uint8_t raw0[kRawBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t raw1[kRawBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t dec_p[kGroups * kPGroup];
+  const int ch = blockIdx.x, part = blockIdx.y;
+  const int sb = part * p.stages_per_split;
+  const int se = min(sb + p.stages_per_split, p.total_stages);
+  if (sb >= se) return;
+  tri_channel_t<kSegments>(p, ch, sb, se, raw0, raw1, dec_p, nullptr, GathSlots{}, &sg);
 }
 
 __global__ __launch_bounds__(kThreads, 1) void xcorr_tri_kernel(TriParams p) {
@@ -715,6 +768,49 @@ hipError_t launch_tri_delayed(const uint8_t* in, int32_t* vis, int n, int f, int
   else
     xcorr_tri_delay_kernel<<<dim3((unsigned)f, (unsigned)split), dim3(kThreads), 0, stream>>>(p,
                                                                                            d);
+  return hipGetLastError();
+}
+
+int tri_max_segments() { return kMaxSegments; }
+
+hipError_t launch_tri_segments(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                               int64_t cs, const int32_t* seg_t0, const int32_t* seg_t_end,
+                               int count, int accumulate, int split, hipStream_t stream) {
+  if (n < 1 || n > kElems || n % 4 != 0) return hipErrorInvalidValue;
+  if (count < 1 || count > kMaxSegments) return hipErrorInvalidValue;
+  TriSegments sg;
+  sg.count = count;
+  int stages = 0;
+  for (int k = 0; k < count; ++k) {
+    if (seg_t0[k] < 0 || seg_t_end[k] <= seg_t0[k] || seg_t_end[k] > t)
+      return hipErrorInvalidValue;
+    sg.t0[k] = seg_t0[k];
+    sg.t_end[k] = seg_t_end[k];
+    sg.stage0[k] = stages;
+    stages += (seg_t_end[k] - seg_t0[k] + kStage - 1) / kStage;
+  }
+  sg.stage0[count] = stages;
+  for (int k = count; k < kMaxSegments; ++k) sg.t0[k] = sg.t_end[k] = 0;
+  TriParams p;
+  p.in = in;
+  p.vis = vis;
+  p.n = n;
+  p.f = f;
+  p.t = t;
+  p.ss = ss;
+  p.cs = cs;
+  p.t0 = 0;
+  p.t_end = t;
+  p.total_stages = stages;
+  if (split < 1) split = 1;
+  if (split > stages) split = stages;
+  p.split = split;
+  p.stages_per_split = (stages + split - 1) / split;
+  p.accumulate = accumulate;
+  p.atomic_out = split > 1;
+  if (f <= 0 || split > 65535) return hipErrorInvalidConfiguration;
+  xcorr_tri_segments_kernel<<<dim3((unsigned)f, (unsigned)split), dim3(kThreads), 0, stream>>>(
+      p, sg);
   return hipGetLastError();
 }
 

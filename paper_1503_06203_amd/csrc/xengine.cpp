@@ -316,7 +316,43 @@ xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates,
   }
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   std::vector<int64_t> held(gates, 0);                           // samples summed in this call
-  for (int64_t k = 0; k < nblocks;) {
+  if (n <= xeng::tri_max_elements() && t > 0) {
+    // Triangle kernel: all runs of one gate in one launch (up to
+    // tri_max_segments() runs each), so a gate's accumulators are read and
+    // written once per launch instead of once per run.
+    std::vector<std::vector<int32_t>> run_t0(gates), run_t1(gates);
+    for (int64_t k = 0; k < nblocks;) {
+      const int g = gate_of_block[k];
+      int64_t e = k + 1;
+      while (e < nblocks && gate_of_block[e] == g) ++e;
+      if (g != 0xFF) {
+        run_t0[g].push_back((int32_t)(k * (int64_t)block));
+        run_t1[g].push_back((int32_t)std::min<int64_t>((int64_t)t, e * (int64_t)block));
+      }
+      k = e;
+    }
+    const int max_seg = xeng::tri_max_segments();
+    for (int g = 0; g < gates; ++g) {
+      int32_t* vis_g = d_vis + (int64_t)g * set_pairs * 2;
+      for (size_t c = 0; c < run_t0[g].size(); c += (size_t)max_seg) {
+        const int cnt = (int)std::min<size_t>((size_t)max_seg, run_t0[g].size() - c);
+        int64_t samples = 0;
+        for (int r = 0; r < cnt; ++r) samples += run_t1[g][c + r] - run_t0[g][c + r];
+        const bool first = !accumulate && held[g] == 0;
+        const int split = xeng::tri_auto_split(f, samples, xeng::device_cu_count());
+        if (first && split > 1) {
+          hipError_t e = xeng::launch_fill_zero(vis_g, set_pairs, stream);
+          if (e != hipSuccess) return device_error(e, "zero fill");
+        }
+        hipError_t e = xeng::launch_tri_segments(d_in, vis_g, n, f, t, n, (int64_t)t * n,
+                                                 run_t0[g].data() + c, run_t1[g].data() + c, cnt,
+                                                 first ? 0 : 1, split, stream);
+        if (e != hipSuccess) return device_error(e, "gated correlation launch");
+        held[g] += samples;
+      }
+    }
+  }
+  for (int64_t k = 0; k < nblocks && n > xeng::tri_max_elements();) {
     const int g = gate_of_block[k];
     int64_t e = k + 1;
     while (e < nblocks && gate_of_block[e] == g) ++e;

@@ -64,3 +64,21 @@ def test_gated_errors():
         xe.correlate_gated(x, vis, [0, 5], 50)               # gate index out of range
     with pytest.raises(xe.XengError):
         xe.correlate_gated(x, vis, [0, 1], 50, t_prev=[xe.MAX_SAMPLES, 0], accumulate=True)
+
+
+# With N <= 256 all runs of one gate go to the triangle kernel in one launch
+# (at most 32 runs per launch): many short runs (several launches per gate),
+# runs not aligned to the 64-sample stages, and one long gate on one channel
+# (split along time, atomic adds).
+@pytest.mark.parametrize("f,t,n,block,gates", [(2, 4096, 64, 8, 2), (1, 16384, 128, 1024, 2),
+                                               (3, 2000, 256, 37, 3)])
+def test_gated_segments(f, t, n, block, gates):
+    print("gated segments f=%d t=%d n=%d block=%d gates=%d" % (f, t, n, block, gates), flush=True)
+    x = synth.quantized_gaussian(f, t, n, 2.5, seed=t + n + block)
+    nb = (t + block - 1) // block
+    sched = (np.arange(nb) % gates).astype(np.uint8)
+    if block == 1024:
+        sched[:] = 0
+        sched[3] = 1
+    got = gated(x.to(DEV), sched, block, gates)
+    assert_same(got, oracle.correlate_gated(x.numpy(), sched, block, gates), "gated segments")

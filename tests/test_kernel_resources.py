@@ -37,7 +37,8 @@ def kernel_field(asm, kernel, field):
 
 def test_triangle_kernel_has_no_scratch_and_fits_lds(tmp_path):
     asm = device_asm("xcorr_tri.hip", tmp_path)
-    for kernel in ("xcorr_tri_kernel", "xcorr_tri_delay_kernel", "xcorr_tri_window_kernel"):
+    for kernel in ("xcorr_tri_kernel", "xcorr_tri_delay_kernel", "xcorr_tri_window_kernel",
+                   "xcorr_tri_segments_kernel"):
         assert kernel_field(asm, kernel, "amdhsa_private_segment_fixed_size") == 0
     for kernel in ("xcorr_tri_kernel", "xcorr_tri_delay_kernel", "xcorr_tri_window_kernel",
                    "xcorr_tri_queue_kernel"):
