@@ -234,9 +234,10 @@ __device__ __forceinline__ void tri_run_bf6(const TriParams& p, int ch, int base
     }
   };
 
-  // One stage st. Four-block waves: load both row groups of st+2, read the
-  // rows of st+1 back transposed and decode them into the other buffer, then
-  // the two MFMA steps. Five-block waves: the two MFMA steps only. Stages past se are loaded and
+  // One stage st. Four-block waves: load both row groups of st+2, then two
+  // steps, each reading one row group of st+1 back transposed, decoding it
+  // into the other buffer and multiplying one step of st. Five-block waves:
+  // the two MFMA steps only. Stages past se are loaded and
   // decoded but never multiplied.
   auto body = [&](auto par, int st) {
     constexpr int kPar = decltype(par)::value;
@@ -248,25 +249,20 @@ __device__ __forceinline__ void tri_run_bf6(const TriParams& p, int ch, int base
     } else {
       fetch2(raw_ld, st + 2);
       vm_wait<16>();   // all but the 16 loads just issued are done: rows of st+1 are in LDS
-      // decode first, multiply after: the operands and the decode never hold
-      // registers together; the five-block wave keeps the matrix core busy
-      // while this one decodes
+      // step g multiplies step g of st while it decodes row group g of st+1
+      // into the other buffer: the decode's VALU work fills the MFMA issue gaps
 #pragma unroll
       for (int g = 0; g < 2; ++g) {
         const int vw = g ? vw1 : vw0;
         const v2i a0 = tr_read(raw_dc, vw, 0), a1 = tr_read(raw_dc, vw, 1);
         const v2i a2 = tr_read(raw_dc, vw, 2), a3 = tr_read(raw_dc, vw, 3);
+        Frags fr;
+        load_frags(fr, kPar, g);
         decode_pair(vw, a0, a1, kPar ^ 1, 0);
         decode_pair(vw, a2, a3, kPar ^ 1, 2);
+        mfma_step(fr);
         __builtin_amdgcn_sched_barrier(0);
       }
-      Frags fr;
-      load_frags(fr, kPar, 0);
-      mfma_step(fr);
-      __builtin_amdgcn_sched_barrier(0);
-      load_frags(fr, kPar, 1);
-      mfma_step(fr);
-      __builtin_amdgcn_sched_barrier(0);
     }
     lds_barrier();
   };
