@@ -506,8 +506,10 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
   // row quads into row_sums in LDS as they decode; MFMA waves sum those of
   // their columns in registers (the two lane halves hold the two K halves).
   uint32_t* const row_sums = reinterpret_cast<uint32_t*>(lds + 2 * kBufBytes);   // [re, im][128]
-  uint32_t col_sr[2] = {0, 0}, col_si[2] = {0, 0};
-  for (int e = tid; e < 2 * kRows; e += kThreads8) row_sums[e] = 0u;
+  uint32_t* const col_sums = row_sums + 2 * kRows;                               // [re, im][256]
+  uint32_t csum_re[4] = {0, 0, 0, 0}, csum_im[4] = {0, 0, 0, 0};
+  uint32_t cbyte_re = 0, cbyte_im = 0;
+  for (int e = tid; e < 2 * kRows + 2 * kCols; e += kThreads8) row_sums[e] = 0u;
   __syncthreads();
 
   struct Frags {
@@ -535,8 +537,6 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
       const uint32_t lo = (uint32_t)fr.rb[cb].x, hi = (uint32_t)fr.rb[cb].y;
       const uint32_t rl = fields_hi(lo), rh = fields_hi(hi), il = fields_lo(lo), ih = fields_lo(hi);
       pb[cb] = v4i{(int)rl, (int)rh, (int)il, (int)ih};
-      col_sr[cb] = __builtin_amdgcn_sad_u8(rh, 0u, __builtin_amdgcn_sad_u8(rl, 0u, col_sr[cb]));
-      col_si[cb] = __builtin_amdgcn_sad_u8(ih, 0u, __builtin_amdgcn_sad_u8(il, 0u, col_si[cb]));
     }
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
@@ -597,13 +597,24 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
         if (seg == 3) decode_rows_fields(tx0, tx1, 1, row_dst0 + buf * kBufBytes, 4 * l32, row_sums);
       } else {
         uint8_t* dst = col_dst0 + buf * kBufBytes;
-        if (seg == 1) {
+        // the column field sums of this wave's 16 rows of the stage, bytes
+        // first (at most 16 * 15 per byte)
+        if (seg == 1 || seg == 2) {
 #pragma unroll
-          for (int r = 0; r < 8; ++r) *reinterpret_cast<uint32_t*>(dst + r * kColRowStride) = dec.w[r];
+          for (int r = 8 * (seg - 1); r < 8 * seg; ++r) {
+            *reinterpret_cast<uint32_t*>(dst + r * kColRowStride) = dec.w[r];
+            cbyte_re += fields_hi(dec.w[r]);
+            cbyte_im += fields_lo(dec.w[r]);
+          }
         }
         if (seg == 2) {
 #pragma unroll
-          for (int r = 8; r < 16; ++r) *reinterpret_cast<uint32_t*>(dst + r * kColRowStride) = dec.w[r];
+          for (int k = 0; k < 4; ++k) {
+            csum_re[k] += (cbyte_re >> (8 * k)) & 0xFFu;
+            csum_im[k] += (cbyte_im >> (8 * k)) & 0xFFu;
+          }
+          cbyte_re = 0;
+          cbyte_im = 0;
         }
       }
     };
@@ -672,7 +683,16 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
   // ---- offset corrections -------------------------------------------------------
   // per row element of the tile: 8 (SR + SI) and 8 (SR - SI), from row_sums;
   // per column: 8 (SR + SI) and 8 SR + 7 SI, from this wave's column sums.
-  // The last stage ended with a barrier, so row_sums is complete.
+  // The last stage ended with a barrier, so row_sums is complete; the column
+  // waves add their column sums now (every wave reaches the barrier below).
+  if (!row_role) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      atomicAdd(col_sums + 4 * lane + k, csum_re[k]);
+      atomicAdd(col_sums + kCols + 4 * lane + k, csum_im[k]);
+    }
+  }
+  __syncthreads();
   if (!wave_active) return;
   // samples this tile summed: stages [stage_begin, stage_end) within t_end
   const int64_t t_first = p.t0 + (int64_t)stage_begin * kStage;
@@ -683,8 +703,8 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
   int32_t* out = p.vis + (int64_t)ch * entries * 2;
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb) {
-    const uint32_t csr = col_sr[cb] + (uint32_t)__shfl_xor((int)col_sr[cb], 32);
-    const uint32_t csi = col_si[cb] + (uint32_t)__shfl_xor((int)col_si[cb], 32);
+    const int jl = wc * 64 + cb * 32 + l32;
+    const uint32_t csr = col_sums[jl], csi = col_sums[kCols + jl];
     const uint32_t re_j = re_const - 8u * (csr + csi);
     const uint32_t ci_j = 8u * csr + 7u * csi;
     const int j = col0 + wc * 64 + cb * 32 + l32;
@@ -715,7 +735,7 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
   }
 }
 __global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes + 2 * kRows * 4];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes + 2 * kRows * 4 + 2 * kCols * 4];
   // With two waves per SIMD each wave has 256 registers. An AGPR operand here
   // tells the compiler the kernel uses accumulation registers, so it splits
   // them 128 VGPR + 128 AGPR and keeps the 128 accumulators out of the VGPRs.
@@ -741,7 +761,7 @@ __global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p)
 // resets the counters, so the workspace is ready for the next launch (no
 // memset, which keeps the launch capturable in a graph).
 __global__ __launch_bounds__(kThreads8, 1) void xcorr_queue_kernel(uint8_t* ws, int hdr_offset) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes + 2 * kRows * 4];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes + 2 * kRows * 4 + 2 * kCols * 4];
   __shared__ int next_item;
   asm volatile("; accumulators live in AGPRs" ::"a"(0));
   QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws + hdr_offset);
