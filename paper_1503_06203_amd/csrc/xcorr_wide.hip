@@ -136,11 +136,12 @@ __device__ inline void decode_rows_half(const uint32_t x0[4], const uint32_t x1[
 }
 
 // Offset form of the row slabs (8-wave kernel): the Excess-8 fields
-// themselves, [uRe g, uRe g+1, uIm g, uIm g+1]; their sums per element are
-// added into sums[0][e] (Re) and sums[1][e] (Im) in LDS (atomic adds: the
-// lanes of the four K steps and two lane halves add into the same element).
+// themselves, [uRe g, uRe g+1, uIm g, uIm g+1]. The per-element field sums
+// are added into sr[k] (Re) and si[k] (Im) for the lane's 4 row elements;
+// the caller folds them into LDS once, after the last stage.
 __device__ inline void decode_rows_fields(const uint32_t x0[4], const uint32_t x1[4], int part,
-                                          uint8_t* pslab, int quad_base, uint32_t* sums) {
+                                          uint8_t* pslab, int quad_base, uint32_t sr[4],
+                                          uint32_t si[4]) {
 #pragma unroll
   for (int kq = 0; kq < 2; ++kq) {
     const int k = 2 * part + kq;
@@ -148,9 +149,8 @@ __device__ inline void decode_rows_fields(const uint32_t x0[4], const uint32_t x
     const uint32_t r0 = fields_hi(x0[k]), r1 = fields_hi(x1[k]);
     const uint32_t i0 = fields_lo(x0[k]), i1 = fields_lo(x1[k]);
     *reinterpret_cast<v4i*>(pslab + slot * 16) = v4i{(int)r0, (int)r1, (int)i0, (int)i1};
-    atomicAdd(sums + quad_base + k, __builtin_amdgcn_sad_u8(r1, 0u, __builtin_amdgcn_sad_u8(r0, 0u, 0u)));
-    atomicAdd(sums + kRows + quad_base + k,
-              __builtin_amdgcn_sad_u8(i1, 0u, __builtin_amdgcn_sad_u8(i0, 0u, 0u)));
+    sr[k] = __builtin_amdgcn_sad_u8(r1, 0u, __builtin_amdgcn_sad_u8(r0, 0u, sr[k]));
+    si[k] = __builtin_amdgcn_sad_u8(i1, 0u, __builtin_amdgcn_sad_u8(i0, 0u, si[k]));
   }
 }
 
@@ -502,13 +502,16 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
       acc_im[rb][cb] = v16i{};
     }
 
-  // Field sums for the offset corrections: row waves add the fields of their
-  // row quads into row_sums in LDS as they decode; MFMA waves sum those of
-  // their columns in registers (the two lane halves hold the two K halves).
+  // Field sums for the offset corrections, kept in registers by the staging
+  // waves and added into row_sums / col_sums in LDS after the last stage: row
+  // waves sum the fields of their 4 row elements as they decode them; column
+  // waves add the fields of their 4 columns over their 16 rows of each stage
+  // bytewise (at most 16 * 15 per byte) and fold them into 32-bit sums.
   uint32_t* const row_sums = reinterpret_cast<uint32_t*>(lds + 2 * kBufBytes);   // [re, im][128]
   uint32_t* const col_sums = row_sums + 2 * kRows;                               // [re, im][256]
   uint32_t csum_re[4] = {0, 0, 0, 0}, csum_im[4] = {0, 0, 0, 0};
   uint32_t cbyte_re = 0, cbyte_im = 0;
+  uint32_t rsum_re[4] = {0, 0, 0, 0}, rsum_im[4] = {0, 0, 0, 0};
   for (int e = tid; e < 2 * kRows + 2 * kCols; e += kThreads8) row_sums[e] = 0u;
   __syncthreads();
 
@@ -593,8 +596,10 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
     auto slice = [&](int seg, Raw16& dec, int buf, uint32_t* tx0, uint32_t* tx1) {
       if (kRow) {
         if (seg == 1) transpose_rows(dec.w, tx0, tx1);
-        if (seg == 2) decode_rows_fields(tx0, tx1, 0, row_dst0 + buf * kBufBytes, 4 * l32, row_sums);
-        if (seg == 3) decode_rows_fields(tx0, tx1, 1, row_dst0 + buf * kBufBytes, 4 * l32, row_sums);
+        if (seg == 2)
+          decode_rows_fields(tx0, tx1, 0, row_dst0 + buf * kBufBytes, 4 * l32, rsum_re, rsum_im);
+        if (seg == 3)
+          decode_rows_fields(tx0, tx1, 1, row_dst0 + buf * kBufBytes, 4 * l32, rsum_re, rsum_im);
       } else {
         uint8_t* dst = col_dst0 + buf * kBufBytes;
         // the column field sums of this wave's 16 rows of the stage, bytes
@@ -683,13 +688,19 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
   // ---- offset corrections -------------------------------------------------------
   // per row element of the tile: 8 (SR + SI) and 8 (SR - SI), from row_sums;
   // per column: 8 (SR + SI) and 8 SR + 7 SI, from this wave's column sums.
-  // The last stage ended with a barrier, so row_sums is complete; the column
-  // waves add their column sums now (every wave reaches the barrier below).
+  // The staging waves add their field sums now (every wave reaches the
+  // barrier below).
   if (!row_role) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       atomicAdd(col_sums + 4 * lane + k, csum_re[k]);
       atomicAdd(col_sums + kCols + 4 * lane + k, csum_im[k]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      atomicAdd(row_sums + 4 * l32 + k, rsum_re[k]);
+      atomicAdd(row_sums + kRows + 4 * l32 + k, rsum_im[k]);
     }
   }
   __syncthreads();
