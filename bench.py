@@ -189,9 +189,10 @@ def bench_gated(w, steps: int, warmup: int):
 def bench_delayed(w, steps: int, warmup: int):
     """Delay compensation on the workload: per-element integer delays drawn
     uniformly from [0, 64] samples (the first element takes the largest), a
-    64-sample halo in front of each channel, and for comparison the same call
-    with all delays equal (no relative shift). The effective rate counts the
-    frame's samples only."""
+    64-sample halo in front of each channel. For comparison the same call with
+    all delays equal (a shifted sample window, run on the dense kernel) and
+    with delays 63 and 64 alternating (the smallest spread the window form
+    stages). The effective rate counts the frame's samples only."""
     import numpy as np
     import torch
 
@@ -214,6 +215,10 @@ def bench_delayed(w, steps: int, warmup: int):
     same = np.full(w.n, dmax, dtype=np.int32)     # the same input, no relative shift
     wall0, _ = time_steps(lambda: xe.correlate_delayed(x, vis, same), steps, warmup)
     out["equal_delays_value"] = round(ops / (wall0 / steps) / 1e12, 3)
+    near = np.full(w.n, dmax, dtype=np.int32)
+    near[1::2] = dmax - 1                         # spread 1: window form
+    wall1, _ = time_steps(lambda: xe.correlate_delayed(x, vis, near), steps, warmup)
+    out["spread1_value"] = round(ops / (wall1 / steps) / 1e12, 3)
     del x, vis
     torch.cuda.empty_cache()
     return out

@@ -159,8 +159,12 @@ xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates,
  *           s of the frame is d_in[.][max_delay + s][.].
  *   delays  host int32_t[n], each in [0, max_delay]; max_delay <= 65535.
  *   d_vis, t_prev, accumulate as for xeng_correlate (t counts frame samples).
- * Runs on the triangle kernel: n <= 256, and t % 64 == 0. Errors as for
- * xeng_correlate; XENG_EINVAL for a delay out of range or t % 64 != 0.
+ * Runs on the triangle kernel: n <= 256, and t % 64 == 0. With n % 4 == 0
+ * and a 4-byte aligned d_in, one delay common to all elements is the plain
+ * correlation of a shifted sample window, and a delay spread of at most 128
+ * samples stages whole rows; otherwise each element's samples are gathered
+ * bytewise (slower, any alignment). Errors as for xeng_correlate; XENG_EINVAL
+ * for a delay out of range or t % 64 != 0.
  */
 xeng_status xeng_correlate_delayed(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
                                    const int32_t* delays, int max_delay, int64_t t_prev,

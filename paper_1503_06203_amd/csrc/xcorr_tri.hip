@@ -742,8 +742,15 @@ hipError_t launch_tri_delayed(const uint8_t* in, int32_t* vis, int n, int f, int
   }
   d.lo = max_delay - dmax;
   d.hi = max_delay - dmin;
-  // the ring loads whole rows with dword loads: n % 4 == 0
-  const bool window = d.hi - d.lo <= kRingSpread && n % 4 == 0;
+  // Dword loads (the dense kernel and the ring) need n % 4 == 0 and a 4-byte
+  // aligned input; otherwise every element is gathered bytewise.
+  const bool dwords = n % 4 == 0 && reinterpret_cast<uintptr_t>(in) % 4 == 0;
+  // One common delay shifts every stream alike: the plain correlation of the
+  // samples [max_delay - delay, max_delay - delay + t) of each channel.
+  if (dwords && dmin == dmax)
+    return launch_tri(in, vis, n, f, t + max_delay, n, (int64_t)(t + max_delay) * n,
+                      max_delay - dmin, t, accumulate, split, stream);
+  const bool window = d.hi - d.lo <= kRingSpread && dwords;
   TriParams p;
   p.in = in;
   p.vis = vis;

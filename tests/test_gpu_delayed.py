@@ -117,3 +117,51 @@ def test_delayed_window_accumulate_matches_gather_form():
     far[5] = 400
     got = delayed(x.to(DEV), far)
     assert_same(got, oracle.correlate_delayed(x.numpy(), far), "gather form")
+
+
+
+@pytest.mark.parametrize("n,d,dmax", [(256, 17, 40), (64, 40, 40), (96, 0, 9)])
+def test_delayed_common_delay(n, d, dmax):
+    # one delay for every element: the shifted-window plain correlation, with
+    # max_delay above the common delay (the C-ABI allows it)
+    import ctypes
+
+    import paper_1503_06203_amd as xe
+    print("common delay n=%d d=%d max_delay=%d" % (n, d, dmax), flush=True)
+    f, t = 2, 512
+    delays = np.full(n, d, dtype=np.int32)
+    x = synth.quantized_gaussian(f, t + dmax, n, 2.5, seed=n + d)
+    xd = x.to(DEV)
+    vis = torch.zeros((f, xe.vis_entries(n), 2), dtype=torch.int32, device=DEV)
+    for acc in (0, 1):
+        xe.check(xe.lib().xeng_correlate_delayed(
+            xd.data_ptr(), vis.data_ptr(), n, f, t, delays.ctypes.data_as(ctypes.c_void_p), dmax,
+            t if acc else 0, acc, xe._stream_ptr(None)))
+    torch.cuda.synchronize()
+    want = oracle.correlate(np.ascontiguousarray(x.numpy()[:, dmax - d: dmax - d + t, :]))
+    assert_same(vis, 2 * want, "common delay, accumulated")
+
+
+def _unaligned(x):
+    # a device copy of x that starts one byte into its allocation
+    flat = torch.empty(x.numel() + 1, dtype=torch.uint8, device=DEV)
+    flat[1:].copy_(x.reshape(-1).to(DEV))
+    view = flat[1:].view(*x.shape)
+    assert view.data_ptr() % 4 == 1
+    return view
+
+
+def test_delayed_unaligned_input():
+    # unaligned input: every element is gathered bytewise
+    f, t, n, dmax = 2, 256, 64, 20
+    print("unaligned delayed f=%d t=%d n=%d" % (f, t, n), flush=True)
+    rng = np.random.default_rng(77)
+    delays = rng.integers(0, dmax + 1, n)
+    delays[0] = dmax
+    x = synth.quantized_gaussian(f, t + dmax, n, 2.5, seed=78)
+    got = delayed(_unaligned(x), delays)
+    assert_same(got, oracle.correlate_delayed(x.numpy(), delays), "unaligned delayed")
+    common = np.full(n, 5, dtype=np.int32)
+    x5 = synth.quantized_gaussian(f, t + 5, n, 2.5, seed=79)
+    got5 = delayed(_unaligned(x5), common)
+    assert_same(got5, oracle.correlate_delayed(x5.numpy(), common), "unaligned common delay")
