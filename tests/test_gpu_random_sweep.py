@@ -1,0 +1,139 @@
+"""Seeded random sweep over every entry point against the oracle: shapes,
+input alignment, time splits, variants, gate schedules and delay spreads
+drawn at random within each entry point's documented limits, with and without
+accumulation. Complements the hand-picked cases of the other GPU tests."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+from gpu_helpers import assert_same  # noqa: E402
+
+
+def _dev_copy(x, off):
+    # device copy of x starting `off` bytes into its allocation
+    flat = torch.empty(x.numel() + off, dtype=torch.uint8, device=DEV)
+    flat[off:].copy_(x.reshape(-1).to(DEV))
+    return flat[off:].view(*x.shape)
+
+
+def _gen(rng, f, t, n, seed):
+    if rng.random() < 0.5:
+        return synth.quantized_gaussian(f, t, n, float(rng.uniform(0.5, 4.0)), seed=seed)
+    return synth.uniform_bytes(f, t, n, seed=seed)
+
+
+def _plain(rng, seed):
+    import paper_1503_06203_amd as xe
+    f, t, n = int(rng.integers(1, 5)), int(rng.integers(0, 2500)), int(rng.integers(1, 520))
+    off, acc = int(rng.integers(0, 4)), bool(rng.random() < 0.3)
+    case = ("plain", f, t, n, off, acc)
+    print(case, flush=True)
+    x = _gen(rng, f, t, n, seed)
+    xd = _dev_copy(x, off)
+    vis = xe.new_vis(n, f)
+    want = oracle.correlate(x.numpy()) if t else np.zeros((f, xe.vis_entries(n), 2), np.int64)
+    if acc:
+        xe.correlate(xd, vis)
+        xe.correlate(xd, vis, t_prev=t, accumulate=True)
+        want = 2 * want
+    else:
+        vis.fill_(7)                       # overwritten, also where t == 0
+        xe.correlate(xd, vis)
+    torch.cuda.synchronize()
+    assert_same(vis, want, str(case))
+
+
+def _variant(rng, seed):
+    import paper_1503_06203_amd as xe
+    v = int(rng.integers(0, len(xe.variants())))
+    n = int(rng.integers(1, 257)) if v in (3, 4) else int(rng.integers(1, 600))
+    if v != 0:
+        n = max(4, n - n % 4)
+    f, t = int(rng.integers(1, 5)), int(rng.integers(1, 3000))
+    split, acc = int(rng.integers(1, 9)), bool(rng.random() < 0.3)
+    case = ("variant", v, f, t, n, split, acc)
+    print(case, flush=True)
+    x = _gen(rng, f, t, n, seed)
+    xd = x.to(DEV)
+    vis = xe.new_vis(n, f)
+    want = oracle.correlate(x.numpy())
+    if acc:
+        xe.correlate(xd, vis)
+        xe.correlate_variant(xd, vis, v, split, t_prev=t, accumulate=True)
+        want = 2 * want
+    else:
+        vis.fill_(-3)
+        xe.correlate_variant(xd, vis, v, split)
+    torch.cuda.synchronize()
+    assert_same(vis, want, str(case))
+
+
+def _strided(rng, seed):
+    import paper_1503_06203_amd as xe
+    f, t, n = int(rng.integers(1, 5)), int(rng.integers(1, 2000)), 4 * int(rng.integers(1, 130))
+    case = ("time-major", f, t, n)
+    print(case, flush=True)
+    dense = _gen(rng, f, t, n, seed)
+    view = dense.permute(1, 0, 2).contiguous().to(DEV).permute(1, 0, 2)
+    vis = xe.new_vis(n, f)
+    xe.correlate(view, vis)
+    torch.cuda.synchronize()
+    assert_same(vis, oracle.correlate(dense.numpy()), str(case))
+
+
+def _gated(rng, seed):
+    import paper_1503_06203_amd as xe
+    gates, n, f = int(rng.integers(1, 5)), 4 * int(rng.integers(1, 100)), int(rng.integers(1, 4))
+    block = int(rng.choice([64, 100, 128, 1000, int(rng.integers(1, 300))]))
+    t = int(rng.integers(1, 3000))
+    sched = rng.integers(0, gates + 1, (t + block - 1) // block).astype(np.uint8)
+    sched[sched == gates] = 0xFF                              # blocks left out
+    case = ("gated", gates, f, t, n, block)
+    print(case, flush=True)
+    x = _gen(rng, f, t, n, seed)
+    vis = torch.full((gates, f, xe.vis_entries(n), 2), 5, dtype=torch.int32, device=DEV)
+    xe.correlate_gated(x.to(DEV), vis, sched, block)
+    torch.cuda.synchronize()
+    assert_same(vis, oracle.correlate_gated(x.numpy(), sched, block, gates), str(case))
+
+
+def _delayed(rng, seed):
+    import paper_1503_06203_amd as xe
+    n, f, t = int(rng.integers(1, 257)), int(rng.integers(1, 4)), 64 * int(rng.integers(1, 30))
+    spread = int(rng.choice([0, 1, 50, 128, 129, 400]))
+    delays = int(rng.integers(0, 50)) + rng.integers(0, spread + 1, n)
+    if rng.random() < 0.3:
+        delays[:] = delays[0]                                 # one common delay
+    off = int(rng.integers(0, 4)) if rng.random() < 0.3 else 0
+    case = ("delayed", f, t, n, spread, off)
+    print(case, flush=True)
+    x = _gen(rng, f, t + int(delays.max()), n, seed)
+    vis = xe.new_vis(n, f)
+    vis.fill_(9)
+    xe.correlate_delayed(_dev_copy(x, off), vis, delays)
+    torch.cuda.synchronize()
+    assert_same(vis, oracle.correlate_delayed(x.numpy(), delays), str(case))
+
+
+@pytest.mark.parametrize("seed", [101, 202, 303])
+def test_random_sweep(seed):
+    rng = np.random.default_rng(seed)
+    kinds = [_plain, _variant, _strided, _gated, _delayed]
+    for _ in range(120):
+        kind = kinds[int(rng.choice(5, p=[0.25, 0.25, 0.15, 0.15, 0.2]))]
+        kind(rng, int(rng.integers(1 << 30)))
