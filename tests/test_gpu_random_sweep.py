@@ -1,7 +1,8 @@
 """Seeded random sweep over every entry point against the oracle: shapes,
 input alignment, time splits, variants, gate schedules and delay spreads
 drawn at random within each entry point's documented limits, with and without
-accumulation. Complements the hand-picked cases of the other GPU tests."""
+accumulation, and batched plans of a few such jobs. Complements the
+hand-picked cases of the other GPU tests."""
 import numpy as np
 import pytest
 import torch
@@ -130,10 +131,37 @@ def _delayed(rng, seed):
     assert_same(vis, oracle.correlate_delayed(x.numpy(), delays), str(case))
 
 
+def _plan(rng, seed):
+    # one persistent launch over a few jobs, some accumulating onto held sums
+    import paper_1503_06203_amd as xe
+    jobs, wants = [], []
+    for k in range(int(rng.integers(1, 7))):
+        n, f, t = 4 * int(rng.integers(1, 150)), int(rng.integers(1, 4)), int(rng.integers(1, 3000))
+        x = _gen(rng, f, t, n, seed + k)
+        want = oracle.correlate(x.numpy())
+        vis = xe.new_vis(n, f)
+        if rng.random() < 0.4:
+            prev = rng.integers(-1000, 1000, tuple(vis.shape)).astype(np.int32)
+            vis.copy_(torch.from_numpy(prev))
+            jobs.append((x.to(DEV), vis, t, True))
+            want = want + prev
+        else:
+            vis.fill_(11)
+            jobs.append((x.to(DEV), vis))
+        wants.append(want)
+    case = ("plan", [tuple(j[0].shape) + (len(j) > 2,) for j in jobs])
+    print(case, flush=True)
+    plan = xe.Plan(jobs)
+    plan.run()
+    torch.cuda.synchronize()
+    for j, want in zip(jobs, wants):
+        assert_same(j[1], want, str(case))
+
+
 @pytest.mark.parametrize("seed", [101, 202, 303])
 def test_random_sweep(seed):
     rng = np.random.default_rng(seed)
-    kinds = [_plain, _variant, _strided, _gated, _delayed]
+    kinds = [_plain, _variant, _strided, _gated, _delayed, _plan]
     for _ in range(120):
-        kind = kinds[int(rng.choice(5, p=[0.25, 0.25, 0.15, 0.15, 0.2]))]
+        kind = kinds[int(rng.choice(6, p=[0.22, 0.22, 0.14, 0.14, 0.18, 0.1]))]
         kind(rng, int(rng.integers(1 << 30)))
