@@ -44,6 +44,9 @@ hipError_t launch_tri(const uint8_t* in, int32_t* vis, int n, int f, int t, int6
 // (max_delay halo samples first); output sample s of element e is input
 // sample s + max_delay - delays[e] (host array of n values in [0, max_delay]).
 // Needs n <= tri_max_elements(), t % tri_stage_samples() == 0, t > 0.
+// Picks the form from the delays: one common delay runs launch_tri on the
+// shifted window, a spread up to 128 the ring (window) form, anything else or
+// a misaligned input the bytewise gather form.
 hipError_t launch_tri_delayed(const uint8_t* in, int32_t* vis, int n, int f, int t,
                               const int32_t* delays, int max_delay, int accumulate, int split,
                               hipStream_t stream);
