@@ -439,13 +439,20 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_wide_kernel(WideParams p) {
 
 
 // ---------------------------------------------------------------------------
-// Two waves per SIMD: the same 128x256 tile, stage layout and LDS formats, but
-// 8 waves of 64x64 (2x2 blocks, 128 accumulators each). The two waves that
-// share a SIMD own the same 64 columns and complementary staging duties
-// (waves 0-3 decode the row panel of K step `wave`, waves 4-7 copy the raw
-// column panel of K step `wave-4`), so while one waits on memory or LDS the
-// other keeps the SIMD's matrix core busy.
+// Two waves per SIMD: the same 128x256 tile and stage length, but 8 waves of
+// 64x64 (2x2 blocks, 128 accumulators each). The two waves that share a SIMD
+// own the same 64 columns and complementary staging duties (waves 0-3 decode
+// the row panel of K step `wave`, waves 4-7 the column panel of K step
+// `wave-4`), so while one waits on memory or LDS the other keeps the SIMD's
+// matrix core busy. Both panels are decoded once per workgroup into 16-byte
+// slabs, so the MFMA steps read both operands ready to use.
 constexpr int kThreads8 = 512;
+// LDS of the 8-wave kernel, per stage buffer: the column panel decoded into
+// 16-byte slabs [uRe g, uRe g+1, uIm g, uIm g+1] per (K step, lane half,
+// column), then the row slabs in the same format; after both buffers the
+// row and column field sums.
+constexpr int kColSlabBytes = kSteps * 2 * kCols * 16;                // 32 KiB
+constexpr int kBufBytes8 = kColSlabBytes + kRowPBytes;
 
 struct Raw16 {
   uint32_t w[16];
@@ -472,8 +479,8 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
   const bool col_ok = col_e < n, row_ok = row_e < n;
   const uint32_t voff_col = (uint32_t)col_e;
   const uint32_t voff_row = (uint32_t)row_e + (uint32_t)(8 * half) * (uint32_t)ss;
-  uint8_t* const col_dst0 = lds + (ks * 16) * kColRowStride + 4 * lane;
-  uint8_t* const row_dst0 = lds + kColRawBytes + ((ks * 2 + half) * kRows) * 16;
+  uint8_t* const col_dst0 = lds + ((ks * 2) * kCols) * 16;     // lane half 0; half 1 follows
+  uint8_t* const row_dst0 = lds + kColSlabBytes + ((ks * 2 + half) * kRows) * 16;
 
   // MFMA roles: rows 64*wr.., columns 64*wc..
   const int wr = wave >> 2, wc = wave & 3;
@@ -489,9 +496,10 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb)
     a_off[rb] = (half * kRows + slot_swizzle(wr * 64 + rb * 32 + l32));
-  const int grp = (lane >> 4) & 3;
-  const int b_off = ((grp >> 1) * 8 + ((lane & 15) >> 1)) * kColRowStride + wc * 64 +
-                    16 * (grp & 1) + 8 * (lane & 1);
+  int b_off[2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+    b_off[cb] = (half * kCols + slot_swizzle(wc * 64 + cb * 32 + l32));
 
   v16i acc_re[2][2], acc_im[2][2];
 #pragma unroll
@@ -503,44 +511,34 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
     }
 
   // Field sums for the offset corrections, kept in registers by the staging
-  // waves and added into row_sums / col_sums in LDS after the last stage: row
-  // waves sum the fields of their 4 row elements as they decode them; column
-  // waves add the fields of their 4 columns over their 16 rows of each stage
-  // bytewise (at most 16 * 15 per byte) and fold them into 32-bit sums.
-  uint32_t* const row_sums = reinterpret_cast<uint32_t*>(lds + 2 * kBufBytes);   // [re, im][128]
+  // waves as they decode (row waves for their 4 row elements, column waves
+  // for their 4 columns) and added into row_sums / col_sums in LDS after the
+  // last stage.
+  uint32_t* const row_sums = reinterpret_cast<uint32_t*>(lds + 2 * kBufBytes8);   // [re, im][128]
   uint32_t* const col_sums = row_sums + 2 * kRows;                               // [re, im][256]
   uint32_t csum_re[4] = {0, 0, 0, 0}, csum_im[4] = {0, 0, 0, 0};
-  uint32_t cbyte_re = 0, cbyte_im = 0;
   uint32_t rsum_re[4] = {0, 0, 0, 0}, rsum_im[4] = {0, 0, 0, 0};
   for (int e = tid; e < 2 * kRows + 2 * kCols; e += kThreads8) row_sums[e] = 0u;
   __syncthreads();
 
   struct Frags {
     v4i pa[2];
-    v2i rb[2];
+    v4i pb[2];
   };
   auto load_frags = [&](Frags& fr, const uint8_t* base, int kk) {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
-      fr.pa[rb] = *reinterpret_cast<const v4i*>(base + kColRawBytes +
+      fr.pa[rb] = *reinterpret_cast<const v4i*>(base + kColSlabBytes +
                                                 (kk * 2 * kRows + a_off[rb]) * 16);
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
-      fr.rb[cb] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
-          (__attribute__((address_space(3))) v2i*)(base + b_off + kk * 16 * kColRowStride +
-                                                   cb * 32));
+      fr.pb[cb] = *reinterpret_cast<const v4i*>(base + (kk * 2 * kCols + b_off[cb]) * 16);
   };
   // Offset arithmetic (Sec. III-A, Eq. 3) on the Excess-8 fields u in [0, 15]:
   // P = [uRe, uIm] both sides, Q = [uIm, 15 - uRe] on the row side; the field
   // sums correct the products in the epilogue.
   auto mfma_step = [&](const Frags& fr) {
-    v4i pb[2];
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const uint32_t lo = (uint32_t)fr.rb[cb].x, hi = (uint32_t)fr.rb[cb].y;
-      const uint32_t rl = fields_hi(lo), rh = fields_hi(hi), il = fields_lo(lo), ih = fields_lo(hi);
-      pb[cb] = v4i{(int)rl, (int)rh, (int)il, (int)ih};
-    }
+    const v4i* const pb = fr.pb;
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
       const v4i qa = {fr.pa[rb].z, fr.pa[rb].w, (int)((uint32_t)fr.pa[rb].x ^ 0x0F0F0F0Fu),
@@ -597,36 +595,29 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
       if (kRow) {
         if (seg == 1) transpose_rows(dec.w, tx0, tx1);
         if (seg == 2)
-          decode_rows_fields(tx0, tx1, 0, row_dst0 + buf * kBufBytes, 4 * l32, rsum_re, rsum_im);
+          decode_rows_fields(tx0, tx1, 0, row_dst0 + buf * kBufBytes8, 4 * l32, rsum_re, rsum_im);
         if (seg == 3)
-          decode_rows_fields(tx0, tx1, 1, row_dst0 + buf * kBufBytes, 4 * l32, rsum_re, rsum_im);
+          decode_rows_fields(tx0, tx1, 1, row_dst0 + buf * kBufBytes8, 4 * l32, rsum_re, rsum_im);
       } else {
-        uint8_t* dst = col_dst0 + buf * kBufBytes;
-        // the column field sums of this wave's 16 rows of the stage, bytes
-        // first (at most 16 * 15 per byte)
-        if (seg == 1 || seg == 2) {
-#pragma unroll
-          for (int r = 8 * (seg - 1); r < 8 * seg; ++r) {
-            *reinterpret_cast<uint32_t*>(dst + r * kColRowStride) = dec.w[r];
-            cbyte_re += fields_hi(dec.w[r]);
-            cbyte_im += fields_lo(dec.w[r]);
-          }
+        // the lane's 4 columns: samples 0-7 (lane half 0 of the MFMA
+        // operands) in slices 1-2, samples 8-15 in slices 2-3
+        uint8_t* const dst = col_dst0 + buf * kBufBytes8;
+        if (seg == 1) {
+          transpose_rows(dec.w, tx0, tx1);
+          decode_rows_fields(tx0, tx1, 0, dst, 4 * lane, csum_re, csum_im);
+          decode_rows_fields(tx0, tx1, 1, dst, 4 * lane, csum_re, csum_im);
         }
         if (seg == 2) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            csum_re[k] += (cbyte_re >> (8 * k)) & 0xFFu;
-            csum_im[k] += (cbyte_im >> (8 * k)) & 0xFFu;
-          }
-          cbyte_re = 0;
-          cbyte_im = 0;
+          transpose_rows(dec.w + 8, tx0, tx1);
+          decode_rows_fields(tx0, tx1, 0, dst + kCols * 16, 4 * lane, csum_re, csum_im);
         }
+        if (seg == 3) decode_rows_fields(tx0, tx1, 1, dst + kCols * 16, 4 * lane, csum_re, csum_im);
       }
     };
     auto body = [&](auto fast_tag, int cur, Raw16& dec, Raw16& ld, int ld_stage, bool do_dec,
                     bool do_ld) {
       constexpr bool kFast = decltype(fast_tag)::value;
-      const uint8_t* base = lds + cur * kBufBytes;
+      const uint8_t* base = lds + cur * kBufBytes8;
       Frags f0, f1;
       uint32_t tx0[4], tx1[4];
       __builtin_amdgcn_sched_barrier(0);
@@ -746,7 +737,7 @@ __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, in
   }
 }
 __global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes + 2 * kRows * 4 + 2 * kCols * 4];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes8 + 2 * kRows * 4 + 2 * kCols * 4];
   // With two waves per SIMD each wave has 256 registers. An AGPR operand here
   // tells the compiler the kernel uses accumulation registers, so it splits
   // them 128 VGPR + 128 AGPR and keeps the 128 accumulators out of the VGPRs.
@@ -772,7 +763,7 @@ __global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p)
 // resets the counters, so the workspace is ready for the next launch (no
 // memset, which keeps the launch capturable in a graph).
 __global__ __launch_bounds__(kThreads8, 1) void xcorr_queue_kernel(uint8_t* ws, int hdr_offset) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes + 2 * kRows * 4 + 2 * kCols * 4];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes8 + 2 * kRows * 4 + 2 * kCols * 4];
   __shared__ int next_item;
   asm volatile("; accumulators live in AGPRs" ::"a"(0));
   QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws + hdr_offset);
