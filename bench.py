@@ -1,18 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the 4-bit X-engine hot path on one MI355X.
 
-A step is one full correlation of one batch of synthetic input that is already
-resident in HBM: for the default workload (CHIME Pathfinder shape, N=256
-elements, F=256 channels, T=16384 samples) one call of the library over the
-whole [F][T][N] block. Prints ONE JSON line:
+A step is one full correlation of one frame of synthetic input that is already
+resident in HBM. The headline workload is the full-CHIME large-N frame
+(N=2048 elements, F=16 channels, T=65536 samples per frame, four frames
+summed into device-resident accumulators in turn): one library call per step.
+Prints ONE JSON line:
 
-  value       effective correlation TOPS = 8 * N(N+1)/2 * F * T / step time
-              (paper Eq. 2 operation count; redundant work is never counted)
-  roofline    the correlation kernel against the int8 MFMA peak, timed with
-              HIP events on the stream it is launched on
+  value        effective correlation TOPS = 8 * N(N+1)/2 * F * T / step time
+               (paper Eq. 2 operation count; redundant work is never counted)
+  roofline     the dominant kernel against the int8 MFMA peak, timed with HIP
+               events on the stream it is launched on; traffic = HBM bytes per
+               launch from the FETCH_SIZE / WRITE_SIZE counters recorded in
+               profiles/ for the current kernel source (null otherwise)
   cpu_baseline the CPU oracle timed on a bounded sample of the same workload
-  secondary   the same measurement on the large-N workload (N=2048, F=16,
-              T=65536 per frame, 4 frames accumulated on the device)
+  pathfinder, tiny, small_n, time_major, gated, delayed, bf6, batched, served
+               secondary measurements (other shapes and entry points)
 """
 from __future__ import annotations
 
@@ -39,6 +42,7 @@ KERNEL_OF_VARIANT = {
     "wide128x256_w4": "xcorr_wide_kernel",
     "wide128x256_w8": "xcorr_wide8_kernel",
     "tri256": "xcorr_tri_kernel",
+    "rect128x256": "xcorr_rect_kernel",
 }
 
 
@@ -258,9 +262,9 @@ def bench_bf6(w, steps: int, warmup: int):
 
 
 def cpu_baseline(w, budget_s: float = 15.0):
-    """Time the CPU oracle on the first k channels of the workload (all N
-    elements and T samples), k chosen from a one-channel calibration so the
-    timed run takes about budget_s."""
+    """Time the CPU oracle on a bounded sample of the workload: whole channels
+    (all N elements, all T samples) as many as fit about budget_s, estimated
+    from a one-channel calibration on a slice of the time axis."""
     import numpy as np
 
     import oracle
@@ -268,27 +272,97 @@ def cpu_baseline(w, budget_s: float = 15.0):
     from paper_1503_06203_amd import metrics
 
     oracle.build(force=False)
-    n_elems = w.n
-    if metrics.effective_ops(w.n, 1, w.t) > 2e12:       # one channel is too much: shrink N
-        n_elems = 256
 
-    def draw(k):
+    def draw(k, t):
         x = synth.quantized_gaussian(k, w.t, w.n, w.sigma, w.seeds()[0], common=w.common)
-        return np.ascontiguousarray(x.numpy()[:, :, :n_elems])
+        return np.ascontiguousarray(x.numpy()[:, :t, :])
 
-    one_ch = draw(1)
+    t_cal = max(1, w.t // 32)
+    cal = draw(1, t_cal)
     t0 = time.perf_counter()
-    oracle.correlate(one_ch)
-    one = time.perf_counter() - t0
-    k = int(max(1, min(w.f, budget_s / max(one, 1e-3))))
-    sample = draw(k)
+    oracle.correlate(cal)
+    per_sample = (time.perf_counter() - t0) / t_cal
+    t_use = w.t
+    if per_sample * w.t > 2 * budget_s:          # one whole channel is too long: fewer samples
+        t_use = max(t_cal, int(budget_s / per_sample))
+    k = int(max(1, min(w.f, budget_s / max(per_sample * t_use, 1e-6))))
+    sample = draw(k, t_use)
     t0 = time.perf_counter()
     oracle.correlate(sample)
     dt = time.perf_counter() - t0
-    ops = metrics.effective_ops(n_elems, k, w.t)
+    ops = metrics.effective_ops(w.n, k, t_use)
     return {"value": ops / dt / 1e12, "unit": "TOPS", "cores": oracle.threads(), "kind": "oracle",
-            "sample": "%d of %d channels, N=%d, T=%d (%.3g effective ops in %.2f s)"
-                      % (k, w.f, n_elems, w.t, ops, dt)}
+            "sample": "%d of %d channels, N=%d, T=%d of %d, first frame (%.3g effective ops "
+                      "in %.2f s)" % (k, w.f, w.n, t_use, w.t, ops, dt)}
+
+
+def mfma_roofline(w, r, digest):
+    """Roofline object for an MFMA-bound workload measured by bench_workload."""
+    kern, vname, vsplit = dispatched_kernel(w.n, w.f, w.t)
+    return {
+        "bound": "mfma",
+        "achieved": round(r["kernel_tops"], 3),
+        "peak": PEAK_INT8_TOPS,
+        "unit": "TOP/s",
+        "frac": round(r["kernel_tops"] / PEAK_INT8_TOPS, 4),
+        "traffic": recorded_traffic(w.name, digest),
+        "kernel": kern,
+        "variant": vname,
+        "time_split": vsplit,
+        "kernel_ms": round(r["kernel_ms"], 5),
+        "algorithmic_ops_per_launch": r["ops_per_step"],
+        "input_gbs": round(r["input_bytes"] / (r["kernel_ms"] / 1e3) / 1e9, 1),
+        "kernel_source": digest,
+    }
+
+
+def bench_small_n(w, steps: int, warmup: int, digest: str):
+    """A small array (N=64): bound by HBM rather than the matrix cores. The
+    roofline is the algorithmic bytes (input read once, output written once)
+    per launch over the launch time, against 8 TB/s."""
+    from paper_1503_06203_amd import metrics
+
+    r = bench_workload(w, steps, warmup)
+    kern, vname, vsplit = dispatched_kernel(w.n, w.f, w.t)
+    alg = metrics.algorithmic_bytes(w.n, w.f, w.t, accumulate=False)
+    gbs = alg / (r["kernel_ms"] / 1e3) / 1e9
+    return {"workload": w.name, "n": w.n, "f": w.f, "t": w.t,
+            "value": round(r["value"], 3), "unit": "TOPS",
+            "ms_per_step": round(r["ms_per_step"], 5),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                         "traffic": recorded_traffic(w.name, digest), "kernel": kern,
+                         "variant": vname, "time_split": vsplit,
+                         "kernel_ms": round(r["kernel_ms"], 5),
+                         "algorithmic_bytes_per_launch": alg,
+                         "mfma_frac": round(r["kernel_tops"] / PEAK_INT8_TOPS, 4)}}
+
+
+def bench_latency(w, calls: int = 200):
+    """Latency of one small correlation (the tiny workload): device time per
+    launch from HIP events, and host time of one call followed by a wait."""
+    import torch
+
+    import paper_1503_06203_amd as xe
+    import synth
+
+    x = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, w.seed, device="cuda:0")
+    vis = xe.new_vis(w.n, w.f, device="cuda:0")
+    wall, per = time_steps(lambda: xe.correlate(x, vis), calls, 20)
+    host = []
+    for _ in range(50):
+        t0 = time.perf_counter()
+        xe.correlate(x, vis)
+        torch.cuda.synchronize()
+        host.append(time.perf_counter() - t0)
+    per_us = sorted(p * 1e6 for p in per)
+    host_us = sorted(h * 1e6 for h in host)
+    kern, vname, _ = dispatched_kernel(w.n, w.f, w.t)
+    return {"workload": w.name, "n": w.n, "f": w.f, "t": w.t, "kernel": kern,
+            "device_us_p50": round(per_us[len(per_us) // 2], 2),
+            "device_us_mean": round(sum(per_us) / len(per_us), 2),
+            "host_call_and_wait_us_p50": round(host_us[len(host_us) // 2], 2),
+            "calls_per_s_back_to_back": round(calls / wall, 1)}
 
 
 def bench_batched(steps: int, warmup: int):
@@ -360,10 +434,10 @@ def bench_served(rate_hz: float = 2000.0, frames: int = 300):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="pathfinder",
-                    choices=["tiny", "pathfinder", "large_n", "batched", "served"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="large_n",
+                    choices=["tiny", "pathfinder", "large_n", "small_n", "batched", "served"])
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-reference", action="store_true",
@@ -387,6 +461,7 @@ def main():
         print(json.dumps(r), flush=True)
         return
 
+    digest = kernel_source_digest()
     w = workloads.WORKLOADS[args.workload]
     r = bench_workload(w, args.steps, args.warmup)
     if args.copy_reference:
@@ -395,9 +470,6 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    digest = kernel_source_digest()
-    traffic = recorded_traffic(w.name, digest)
-    kern, vname, vsplit = dispatched_kernel(w.n, w.f, w.t)
     line = {
         "metric": "effective correlation TOPS (8 ops/complex MAC) + % int8 MFMA peak",
         "value": round(r["value"], 3),
@@ -412,38 +484,29 @@ def main():
         "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "f": w.f, "t": w.t, "sigma": w.sigma,
-                   "common": w.common, "frames": len(w.seeds()), "input": "uint8[F][T][N] 4+4-bit",
+                   "common": w.common, "frames": len(w.seeds()),
+                   "frame_order": "frames cycle; the first of each cycle overwrites the "
+                                  "accumulators, the others add to them",
+                   "input": "uint8[F][T][N] 4+4-bit",
                    "output": "int32[F][N(N+1)/2][2]", "parallelism": "single-gpu"},
         "pct_int8_peak": round(100 * r["value"] / PEAK_INT8_TOPS, 2),
-        "roofline": {
-            "bound": "mfma",
-            "achieved": round(r["kernel_tops"], 3),
-            "peak": PEAK_INT8_TOPS,
-            "unit": "TOP/s",
-            "frac": round(r["kernel_tops"] / PEAK_INT8_TOPS, 4),
-            "traffic": traffic,
-            "kernel": kern,
-            "variant": vname,
-            "time_split": vsplit,
-            "kernel_ms": round(r["kernel_ms"], 5),
-            "algorithmic_ops_per_launch": r["ops_per_step"],
-            "input_gbs": round(r["input_bytes"] / (r["kernel_ms"] / 1e3) / 1e9, 1),
-            "kernel_source": digest,
-        },
+        "roofline": mfma_roofline(w, r, digest),
     }
-    if not args.no_secondary and w.name == "pathfinder":
-        line["time_major"] = bench_time_major(w, 20, 3)
-        line["gated"] = bench_gated(w, 10, 2)
-        line["delayed"] = bench_delayed(w, 10, 2)
-        line["bf6"] = bench_bf6(w, 20, 3)
-    if not args.no_secondary and w.name != "large_n":
-        lw = workloads.LARGE_N
-        s = bench_workload(lw, 8, 2)
-        line["secondary"] = {"workload": lw.name, "n": lw.n, "f": lw.f, "t": lw.t,
-                             "frames": len(lw.seeds()), "value": round(s["value"], 3),
-                             "unit": "TOPS", "ms_per_step": round(s["ms_per_step"], 4),
-                             "kernel_tops": round(s["kernel_tops"], 3),
-                             "frac_int8_peak": round(s["kernel_tops"] / PEAK_INT8_TOPS, 4)}
+    if w.name == "small_n":
+        line["roofline"] = bench_small_n(w, args.steps, args.warmup, digest)["roofline"]
+    if not args.no_secondary and w.name == "large_n":
+        pw = workloads.PATHFINDER
+        pr = bench_workload(pw, 20, 3)
+        line["pathfinder"] = {"workload": pw.name, "n": pw.n, "f": pw.f, "t": pw.t,
+                              "value": round(pr["value"], 3), "unit": "TOPS",
+                              "ms_per_step": round(pr["ms_per_step"], 5),
+                              "roofline": mfma_roofline(pw, pr, digest)}
+        line["tiny"] = bench_latency(workloads.TINY)
+        line["small_n"] = bench_small_n(workloads.SMALL_N, 20, 3, digest)
+        line["time_major"] = bench_time_major(pw, 20, 3)
+        line["gated"] = bench_gated(pw, 10, 2)
+        line["delayed"] = bench_delayed(pw, 10, 2)
+        line["bf6"] = bench_bf6(pw, 20, 3)
         line["batched"] = bench_batched(10, 2)
         line["served"] = bench_served()
     if not args.no_cpu_baseline:

@@ -101,6 +101,10 @@ xeng_status xeng_correlate(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
  *     4-bit values (Sec. III) are exact in the 6-bit float E3M2 and partial
  *     sums are exact in fp32 below 2^24, so each workgroup sums at most
  *     131 008 samples; split_t is raised to that bound where needed.
+ *   5 rect128x256_tri256_w8_kc64_mfma32x32x32  n % 4 == 0, aligned input: the
+ *     triangle cut into 256-element diagonal squares (the blocks of variant 3)
+ *     and 128 x 256 tiles wholly above them (Sec. II-C: only tiles that reach
+ *     the upper triangle are computed); the default for n > 256.
  */
 int xeng_variant_count(void);
 const char* xeng_variant_name(int variant);   /* NULL if out of range */
@@ -174,8 +178,8 @@ xeng_status xeng_correlate_delayed(const uint8_t* d_in, int32_t* d_vis, int n, i
  * The variant and time split xeng_correlate would use for a job of this shape
  * (host only, no device work). input_aligned: the input pointer is 4-byte
  * aligned. Kernels: tri256 (n <= 256, n % 4 == 0, aligned input: one workgroup
- * per channel covers the whole triangle), wide128x256_w8 (other aligned n % 4
- * == 0 jobs), tile128 (everything else). Returns XENG_EINVAL for n < 1, f < 1
+ * per channel covers the whole triangle), rect128x256_tri256 (other aligned
+ * n % 4 == 0 jobs), tile128 (everything else). Returns XENG_EINVAL for n < 1, f < 1
  * or t < 0, or a NULL output pointer.
  */
 xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* variant,
@@ -184,12 +188,13 @@ xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* var
 /* ---- Batched mode: many jobs in one persistent launch ------------------------
  * A plan holds a list of independent correlation jobs (each as for
  * xeng_correlate) of mixed n, f and t and runs them all with one launch of a
- * persistent kernel that pulls tiles (channel, 128x256 tile, range of time
- * stages) from a queue in device memory. Results are bit-identical to one
+ * persistent kernel that pulls pieces (channel, 256-element diagonal square
+ * or 128x256 tile above the squares, range of time stages) from a queue in
+ * device memory. Results are bit-identical to one
  * xeng_correlate per job. Jobs need n % 4 == 0 and 4-byte aligned inputs; the
  * outputs of different jobs must not overlap.
  *
- * The plan's device image (job table, tile queue, counters) lives in a
+ * The plan's device image (job table, piece queue, counters) lives in a
  * workspace of xeng_plan_workspace_bytes() bytes that the caller allocates and
  * passes in; the library keeps no device memory. Order of calls:
  *   xeng_plan_create -> xeng_plan_upload (copies the image, stream-ordered)
@@ -216,7 +221,7 @@ xeng_status xeng_plan_create(xeng_plan** out, const xeng_job* jobs, int njobs,
 /* Workspace bytes for the plan; enough for every time split the autotuner may
  * choose, so one allocation serves the plan for its whole life. */
 size_t xeng_plan_workspace_bytes(const xeng_plan* plan);
-int64_t xeng_plan_items(const xeng_plan* plan);   /* tiles in the queue; -1 if plan is NULL */
+int64_t xeng_plan_items(const xeng_plan* plan);   /* pieces in the queue; -1 if plan is NULL */
 int xeng_plan_split(const xeng_plan* plan);       /* stages are split this many ways per tile */
 xeng_status xeng_plan_upload(xeng_plan* plan, void* d_workspace, void* hip_stream);
 /* Rebind every job to a new frame: d_in[k] (NULL keeps the inputs) and
@@ -229,8 +234,12 @@ xeng_status xeng_plan_run(xeng_plan* plan, void* d_workspace, void* hip_stream);
 xeng_status xeng_plan_graph_capture(xeng_plan* plan, void* d_workspace);
 xeng_status xeng_plan_graph_launch(xeng_plan* plan, void* hip_stream);
 /* Time the plan with several time splits per tile (running it reps times
- * each, writing the jobs' outputs), keep the fastest, re-upload, and append the
- * choice to tune_cache_path (may be NULL). best_ms may be NULL. */
+ * each), keep the fastest, re-upload, and append the choice to tune_cache_path
+ * (may be NULL). best_ms may be NULL. Every timed run overwrites the jobs'
+ * outputs with the correlation of their current inputs, so the plan's jobs
+ * must all overwrite (accumulate = 0): a plan with an accumulating job is
+ * refused with XENG_EINVAL and nothing runs. On success the outputs hold one
+ * frame's sums, as after one xeng_plan_run. */
 xeng_status xeng_plan_autotune(xeng_plan* plan, void* d_workspace, void* hip_stream, int reps,
                                const char* tune_cache_path, float* best_ms);
 void xeng_plan_destroy(xeng_plan* plan);
@@ -251,8 +260,9 @@ void xeng_plan_destroy(xeng_plan* plan);
  * would push the open accumulators past hbm_budget bytes; a frame is launched
  * only while accumulators plus frames in flight stay within hbm_budget, and
  * otherwise waits. The workspace (ws_bytes of caller device memory, split in
- * max_inflight slots) holds the per-step tile queues. Served jobs need
- * n % 4 == 0; frames need 4-byte aligned input and 1 <= t <= 1 048 512.
+ * max_inflight slots) holds the per-step queues. Served jobs need n % 4 == 0;
+ * frames need 4-byte aligned input and t >= 1 (a job's samples stay within
+ * XENG_MAX_SAMPLES).
  * Frame buffers must stay valid until their ticket is done. Latency is
  * measured from xeng_submit to the device-side completion of the frame's step.
  */

@@ -31,6 +31,18 @@ hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int
 int64_t wide_max_samples_per_launch();
 int64_t wide_tiles_per_channel(int n);
 
+// Kernel for arrays of any size (n % 4 == 0, 4-byte aligned input; meant for
+// n > 256): each channel is cut into rect_units_per_channel(n) pieces, the
+// 256-element diagonal squares (the triangle kernel's block programs) and the
+// 128x256 tiles above them. Sums samples [t0, t0 + t_count); sums are
+// unscaled, so one launch may cover any t_count. split > 1 divides the time
+// axis and combines with int32 atomic adds (the caller zero-fills vis first
+// when not accumulating).
+hipError_t launch_rect(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                       int64_t cs, int t0, int t_count, int accumulate, int split,
+                       hipStream_t stream);
+int64_t rect_units_per_channel(int n);
+
 // Triangle kernel for n <= tri_max_elements() (n % 4 == 0, 4-byte aligned
 // input): one workgroup per channel (times split) computes the channel's whole
 // upper triangle. Sums samples [t0, t0 + t_count) of each channel; sums are
@@ -68,46 +80,42 @@ int tri_max_segments();
 int tri_max_elements();
 int tri_stage_samples();
 
-// ---- batched mode: persistent launches over queues of work items --------------
-// Device-side images written by the host (plans, the server) into the caller's
-// workspace. Jobs with n <= tri_max_elements() run on the triangle kernel (one
-// item = one channel over a range of stages), the others on 128x256 tiles (one
-// item = one tile of one channel over a range of stages). Each kind has its own
-// queue header; both share one job table:
-//   [header, triangle items][header, tile items][job table][triangle items][tile items]
-struct QueueJob {            // one correlation job (one launch window of it)
+// ---- batched mode: persistent launches over a queue of work items -------------
+// Device-side image written by the host (plans, the server) into the caller's
+// workspace: [header][job table][items]. Every job is cut into the pieces of
+// launch_rect (one diagonal square per 256 elements and the tiles above
+// them; a job of at most 256 elements is one square, the triangle kernel's
+// work); one item = one piece of one channel over a range of stages.
+struct QueueJob {            // one correlation job (one window of its samples)
   const uint8_t* in;
   int32_t* vis;
   int n, f, t;               // elements, channels, samples per channel
   int64_t ss, cs;            // bytes from one sample to the next, one channel to the next
   int t0, t_end;             // window of samples this job sums
-  int nbr, ntiles, total_stages;
-  int accumulate, atomic_out, full_panels;
+  int nbc, units, total_stages;   // 256-element blocks, pieces per channel, stages
+  int accumulate, atomic_out;
   int zero_first;            // zero vis before the queue runs (atomic sums, not accumulating)
 };
-struct QueueItem {           // one tile (or whole triangle) of one channel over a range of stages
-  int job, ch, tile, stage_begin, stage_end, pad[3];
+struct QueueItem {           // one piece of one channel over a range of stages
+  int job, ch, unit, stage_begin, stage_end, pad[3];
 };
 constexpr int kQueueParts = 8;   // one sub-queue per XCD
-constexpr int kQueueTri = 0, kQueueWide = 1, kQueueKinds = 2;
 constexpr int kQueueHeaderStride = 256;
 struct QueueHeader {
   unsigned cursor[kQueueParts];  // next item of each sub-queue (self-resetting)
   unsigned done;                 // workgroups that have finished (self-resetting)
   int part_begin[kQueueParts + 1];  // items of sub-queue k: [part_begin[k], part_begin[k+1])
   int jobs_offset;               // byte offset of the QueueJob array
-  int items_offset;              // byte offset of this kind's QueueItem array
+  int items_offset;              // byte offset of the QueueItem array
   int pad[5];
 };
 static_assert(sizeof(QueueHeader) <= kQueueHeaderStride, "queue header size");
-// Byte offsets of the job table and of the first item array in a queue image.
-__host__ __device__ inline size_t queue_jobs_offset() {
-  return (size_t)kQueueKinds * kQueueHeaderStride;
-}
+// Byte offsets of the job table and of the item array in a queue image.
+__host__ __device__ inline size_t queue_jobs_offset() { return (size_t)kQueueHeaderStride; }
 __host__ __device__ inline size_t queue_items_offset(int njobs) {
   return (queue_jobs_offset() + sizeof(QueueJob) * (size_t)njobs + 255) / 256 * 256;
 }
-// The header's offsets and item ranges, the item lists and the job table are
+// The header's offsets and item ranges, the item list and the job table are
 // not written while a queue kernel runs (only cursor and done are, by atomics),
 // so kernels read them through the constant address space: scalar loads, whose
 // results stay in scalar registers and keep buffer descriptors scalar.
@@ -115,49 +123,14 @@ typedef const __attribute__((address_space(4))) QueueHeader* QueueHeaderC;
 typedef const __attribute__((address_space(4))) QueueItem* QueueItemC;
 typedef const __attribute__((address_space(4))) QueueJob* QueueJobC;
 
-__device__ inline QueueItem load_item(QueueItemC items, int k) {
-  QueueItem q;
-  q.job = items[k].job;
-  q.ch = items[k].ch;
-  q.tile = items[k].tile;
-  q.stage_begin = items[k].stage_begin;
-  q.stage_end = items[k].stage_end;
-  return q;
-}
-__device__ inline QueueJob load_job(QueueJobC jobs, int k) {
-  QueueJob J;
-  J.in = jobs[k].in;
-  J.vis = jobs[k].vis;
-  J.n = jobs[k].n;
-  J.f = jobs[k].f;
-  J.t = jobs[k].t;
-  J.ss = jobs[k].ss;
-  J.cs = jobs[k].cs;
-  J.t0 = jobs[k].t0;
-  J.t_end = jobs[k].t_end;
-  J.nbr = jobs[k].nbr;
-  J.ntiles = jobs[k].ntiles;
-  J.total_stages = jobs[k].total_stages;
-  J.accumulate = jobs[k].accumulate;
-  J.atomic_out = jobs[k].atomic_out;
-  J.full_panels = jobs[k].full_panels;
-  J.zero_first = jobs[k].zero_first;
-  return J;
-}
-
 int queue_stage_samples();
-int64_t queue_tiles_per_channel(int n);
-int queue_kind_of(int n);
-// Build the image for job table `table` with `split` stage ranges per tile
-// (items[k] receives the item count of kind k). The job table must already
-// hold n, f, t0, t_end, total_stages and ntiles.
+// Build the image for job table `table` with `split` stage ranges per piece
+// (*items_out receives the item count). The job table must already hold n, f,
+// t0, t_end, total_stages, nbc and units.
 void build_queue_image(const QueueJob* table, int njobs, int split, uint8_t** image_out,
-                       size_t* bytes_out, int64_t items[kQueueKinds]);
-// One persistent launch per kind with items, in order, on `stream`; grid =
-// workgroups (one per compute unit).
-hipError_t launch_queues(void* d_ws, const int64_t items[kQueueKinds], int grid,
-                         hipStream_t stream);
-hipError_t launch_queue_wide(void* d_ws, int header_offset, int grid, hipStream_t stream);
-hipError_t launch_queue_tri(void* d_ws, int header_offset, int grid, hipStream_t stream);
+                       size_t* bytes_out, int64_t* items_out);
+// One persistent launch over the image's items (nothing if items == 0), on
+// `stream`; grid = workgroups (one per compute unit).
+hipError_t launch_queue(void* d_ws, int64_t items, int grid, hipStream_t stream);
 
 }  // namespace xeng

@@ -372,6 +372,8 @@ hipError_t launch_tri_bf6(const uint8_t* in, int32_t* vis, int n, int f, int t, 
   p.in = in;
   p.vis = vis;
   p.n = n;
+  p.e0 = 0;
+  p.n_total = p.n;
   p.f = f;
   p.t = t;
   p.ss = ss;

@@ -22,7 +22,9 @@ constexpr uint32_t kOob = 0x80000000u;          // buffer offset past every reco
 struct TriParams {
   const uint8_t* in;
   int32_t* vis;
-  int n, f;
+  int n, f;              // elements of this triangle, channels
+  int e0;                // first element of the triangle (a multiple of 4)
+  int n_total;           // elements of the whole array (output indexing)
   int t;                 // samples per channel
   int64_t ss, cs;        // bytes from one sample to the next, and from one channel to the next
   int t0, t_end;         // this launch sums samples [t0, t_end)
@@ -74,6 +76,18 @@ struct ProgB<3> {  // (4,4) (4,5) (4,6) (4,7)
   static constexpr int sa[kNS] = {0, 0, 0, 0};
   static constexpr int sb[kNS] = {0, 1, 2, 3};
 };
+
+// The thread index, through an empty asm statement the compiler cannot see
+// through or move: values derived from it are then computed where they are
+// used. In a persistent kernel, which runs this code once per queue item,
+// the compiler would otherwise compute every lane offset of every code path
+// once, before the item loop, and hold them all in registers for its whole
+// length.
+__device__ inline int opaque_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 typedef __attribute__((address_space(3))) v2i* lds_v2i_ptr;

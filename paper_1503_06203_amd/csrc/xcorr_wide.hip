@@ -459,7 +459,7 @@ struct Raw16 {
 };
 
 // One tile of one channel over stages [stage_begin, stage_end) of the launch
-// window in p. Shared by the per-tile kernel and the persistent queue kernel.
+// window in p.
 __device__ __forceinline__ void wide8_tile(const WideParams& p, uint8_t* lds, int ch, int bi,
                                            int bj, int stage_begin, int stage_end) {
   const int row0 = bi * kRows, col0 = bj * kCols;
@@ -756,79 +756,6 @@ __global__ __launch_bounds__(kThreads8, 1) void xcorr_wide8_kernel(WideParams p)
 }
 
 
-// Persistent workgroups over a queue of tiles of many jobs (batched mode).
-// Workgroup w serves sub-queue w % 8 (the XCD it runs on, so neighbouring
-// tiles of a channel share that XCD's L2) and then steals from the others.
-// Every workgroup leaves once all sub-queues are empty; the last one out
-// resets the counters, so the workspace is ready for the next launch (no
-// memset, which keeps the launch capturable in a graph).
-__global__ __launch_bounds__(kThreads8, 1) void xcorr_queue_kernel(uint8_t* ws, int hdr_offset) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kBufBytes8 + 2 * kRows * 4 + 2 * kCols * 4];
-  __shared__ int next_item;
-  asm volatile("; accumulators live in AGPRs" ::"a"(0));
-  QueueHeader* hdr = reinterpret_cast<QueueHeader*>(ws + hdr_offset);
-  const QueueHeaderC hdr_c = (QueueHeaderC)(ws + hdr_offset);
-  const QueueJobC jobs = (QueueJobC)(ws + hdr_c->jobs_offset);
-  const QueueItemC items = (QueueItemC)(ws + hdr_c->items_offset);
-  int part = blockIdx.x % kQueueParts, tried = 0;
-  while (true) {
-    if (threadIdx.x == 0) {
-      int it = -1;
-      while (tried < kQueueParts) {
-        const int b = hdr_c->part_begin[part], e = hdr_c->part_begin[part + 1];
-        if (b < e) {
-          const unsigned k = atomicAdd(&hdr->cursor[part], 1u);
-          if ((int)k < e - b) {
-            it = b + (int)k;
-            break;
-          }
-        }
-        part = (part + 1) % kQueueParts;
-        ++tried;
-      }
-      next_item = it;
-    }
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(next_item);
-    __syncthreads();
-    if (it < 0) break;
-    const QueueItem q = load_item(items, it);
-    const QueueJob J = load_job(jobs, q.job);
-    WideParams p;
-    p.in = J.in;
-    p.vis = J.vis;
-    p.n = J.n;
-    p.f = J.f;
-    p.t = J.t;
-    p.ss = J.ss;
-    p.cs = J.cs;
-    p.t0 = J.t0;
-    p.t_end = J.t_end;
-    p.nbr = J.nbr;
-    p.nbc = 0;
-    p.ntiles = J.ntiles;
-    p.split = 1;
-    p.stages_per_split = J.total_stages;
-    p.total_stages = J.total_stages;
-    p.accumulate = J.accumulate;
-    p.atomic_out = J.atomic_out;
-    p.full_panels = J.full_panels;
-    int bi, bj;
-    tile_coords(q.tile, p.nbr, &bi, &bj);
-    wide8_tile(p, lds, q.ch, bi, bj, q.stage_begin, q.stage_end);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned d = atomicAdd(&hdr->done, 1u);
-    if (d == gridDim.x - 1) {
-      for (int k = 0; k < kQueueParts; ++k) hdr->cursor[k] = 0u;
-      hdr->done = 0u;
-      __threadfence();
-    }
-  }
-}
-
 }  // namespace
 
 int64_t wide_tiles_per_channel(int n) {
@@ -840,15 +767,6 @@ int64_t wide_tiles_per_channel(int n) {
 
 int64_t wide_max_samples_per_launch() { return kMaxSamplesPerLaunch; }
 
-int queue_stage_samples() { return kStage; }
-int64_t queue_tiles_per_channel(int n) { return wide_tiles_per_channel(n); }
-
-hipError_t launch_queue_wide(void* d_ws, int header_offset, int grid, hipStream_t stream) {
-  if (grid <= 0) return hipErrorInvalidConfiguration;
-  xcorr_queue_kernel<<<dim3((unsigned)grid), dim3(kThreads8), 0, stream>>>(
-      reinterpret_cast<uint8_t*>(d_ws), header_offset);
-  return hipGetLastError();
-}
 
 hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
                        int64_t cs, int t0, int t_count, int accumulate, int split, int waves,

@@ -69,6 +69,11 @@ int tri_auto_split(int f, int64_t t_count, int cus) {
   return auto_split(f, (t_count + stage - 1) / stage, cus);
 }
 
+int rect_auto_split(int n, int f, int64_t t_count, int cus) {
+  const int64_t stage = tri_stage_samples();
+  return auto_split(rect_units_per_channel(n) * f, (t_count + stage - 1) / stage, cus);
+}
+
 int wide_auto_split(int n, int f, int64_t t_count, int cus) {
   const int64_t stage = queue_stage_samples();
   const int64_t win = wide_max_samples_per_launch();
@@ -94,20 +99,23 @@ const Variant kVariants[] = {
     {"wide128x256_w8_kc64_mfma32x32x32"}, // n % 4 == 0, 4-byte aligned input
     {"tri256_w8_kc64_mfma32x32x32"},      // n <= 256, n % 4 == 0, 4-byte aligned input
     {"tri256_w8_bf6_mfma32x32x64"},       // as above, on bf6 operands (exact)
+    {"rect128x256_tri256_w8_kc64_mfma32x32x32"},  // n % 4 == 0, 4-byte aligned input
 };
 constexpr int kVariantTile128 = 0;
 constexpr int kVariantWide = 1;
 constexpr int kVariantWide8 = 2;
 constexpr int kVariantTri = 3;
 constexpr int kVariantTriBf6 = 4;
+constexpr int kVariantRect = 5;
 constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // The kernel xeng_correlate uses: the triangle kernel where it applies (it
-// wastes the least MFMA work on small arrays), else the wide kernel for
-// dword-loadable inputs, else the general one.
+// wastes the least MFMA work on small arrays), else the kernel of diagonal
+// squares and off-diagonal tiles for dword-loadable inputs, else the general
+// one.
 int default_variant(int n, bool aligned) {
   if (aligned && n <= xeng::tri_max_elements()) return kVariantTri;
-  return aligned ? kVariantWide8 : kVariantTile128;
+  return aligned ? kVariantRect : kVariantTile128;
 }
 
 bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
@@ -222,6 +230,10 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
                 kVariants[variant].name);
   if (wide && (int64_t)n * 32 >= ((int64_t)1 << 31))
     return fail(XENG_EINVAL, "variant %s supports n < 2^26", kVariants[variant].name);
+  const bool rect = variant == kVariantRect;
+  if (rect && !aligned)
+    return fail(XENG_EINVAL, "variant %s needs n %% 4 == 0 and a 4-byte aligned input",
+                kVariants[variant].name);
   const bool tri = variant == kVariantTri || variant == kVariantTriBf6;
   if (tri && !tri_ok)
     return fail(XENG_EINVAL, "variant %s needs n <= %d, n %% 4 == 0 and a 4-byte aligned input",
@@ -232,6 +244,7 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
   if (variant == kVariantTriBf6) split = std::max(split, xeng::tri_bf6_min_split(t));
   if (variant == kVariantWide8 && split_t == 0)
     split = xeng::wide_auto_split(n, f, t, xeng::device_cu_count());
+  if (rect && split_t == 0) split = xeng::rect_auto_split(n, f, t, xeng::device_cu_count());
   if (split > 1 && !accumulate) {
     hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
     if (e != hipSuccess) return device_error(e, "zero fill");
@@ -239,6 +252,8 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
   hipError_t e = hipSuccess;
   if (variant == kVariantTri) {
     e = xeng::launch_tri(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
+  } else if (rect) {
+    e = xeng::launch_rect(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
   } else if (variant == kVariantTriBf6) {
     e = xeng::launch_tri_bf6(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
   } else if (wide) {
@@ -430,6 +445,7 @@ xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* var
   *split_t = 1;
   if (v == kVariantTri && t > 0) *split_t = xeng::tri_auto_split(f, t, xeng::device_cu_count());
   if (v == kVariantWide8 && t > 0) *split_t = xeng::wide_auto_split(n, f, t, xeng::device_cu_count());
+  if (v == kVariantRect && t > 0) *split_t = xeng::rect_auto_split(n, f, t, xeng::device_cu_count());
   return XENG_OK;
 }
 

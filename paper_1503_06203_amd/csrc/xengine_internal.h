@@ -29,5 +29,6 @@ int auto_split(int64_t units, int64_t stages, int cus);
 // The split for the triangle kernel and for the 8-wave wide kernel.
 int tri_auto_split(int f, int64_t t_count, int cus);
 int wide_auto_split(int n, int f, int64_t t_count, int cus);
+int rect_auto_split(int n, int f, int64_t t_count, int cus);
 
 }  // namespace xeng

@@ -1,11 +1,12 @@
 // xengine_plan.cpp -- batched mode: many correlation jobs of mixed size in one
 // persistent launch over a flattened queue of tiles (the xeng_plan_* ABI).
 //
-// A plan turns each job into "windows" of at most wide_max_samples_per_launch()
-// samples and each window into items (channel, tile, range of stages). Items
-// are ordered largest first, job by job and channel by channel (so tiles that
-// share input panels stay together), and cut into kQueueParts contiguous
-// sub-queues of about equal cost, one per XCD. The host builds the device
+// A plan turns each job into items (channel, piece, range of stages): the
+// pieces are the 256-element diagonal squares and the 128 x 256 tiles above
+// them (a job of at most 256 elements is one square). Items are ordered
+// largest first, job by job and channel by channel (so pieces that share
+// input panels stay together), and cut into kQueueParts contiguous sub-queues
+// of about equal cost, one per XCD. The host builds the device
 // image once; uploading it into the caller's workspace is the only copy. A run
 // is then pure kernel launches (an optional zero fill, the queue kernel), so it
 // can be captured in a HIP graph and replayed frame after frame; a new frame
@@ -60,12 +61,17 @@ struct xeng_plan {
   std::vector<xeng_job> jobs;
   std::vector<int64_t> held;       // samples each job's sums hold after the configured frame
   std::vector<xeng::PlanWindow> windows;
-  int64_t items[xeng::kQueueKinds] = {0, 0};   // triangle items, tile items
+  int64_t items = 0;               // queue items
   std::vector<uint8_t> image;      // headers + job table + items, as uploaded
   int split = 1;                   // stage split per item (autotuned)
   size_t ws_bytes = 0;             // workspace for the largest split the tuner tries
   int grid = 0;
-  bool needs_fill = false;
+  // Some window combines partial sums with atomic adds. Such windows need a
+  // zero fill whenever their job overwrites; the fill kernel is then part of
+  // every run (and of a captured graph), and it reads each job's zero_first
+  // flag on the device, so a later xeng_plan_set_frame that switches a job
+  // between accumulating and overwriting needs no new capture.
+  bool any_atomic = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   void* graph_ws = nullptr;
@@ -78,7 +84,7 @@ namespace {
 std::vector<QueueJob> job_table(xeng_plan* pl) {
   const int stage = queue_stage_samples();
   std::vector<QueueJob> table;
-  pl->needs_fill = false;
+  pl->any_atomic = false;
   for (size_t w = 0; w < pl->windows.size(); ++w) {
     const auto& win = pl->windows[w];
     const xeng_job& job = pl->jobs[win.job];
@@ -94,14 +100,13 @@ std::vector<QueueJob> job_table(xeng_plan* pl) {
     J.cs = (int64_t)job.t * job.n;
     J.t0 = win.t0;
     J.t_end = win.t_end;
-    J.nbr = (job.n + 127) / 128;
-    J.ntiles = (int)queue_tiles_per_channel(job.n);
+    J.nbc = (job.n + 255) / 256;
+    J.units = J.nbc * J.nbc;
     J.total_stages = (win.t_end - win.t0 + stage - 1) / stage;
     J.atomic_out = (nwin > 1 || pl->split > 1) ? 1 : 0;
     J.accumulate = job.accumulate;
-    J.full_panels = (job.n % 256) == 0;
     J.zero_first = (J.atomic_out && !job.accumulate && win.first) ? 1 : 0;
-    pl->needs_fill |= J.zero_first != 0;
+    pl->any_atomic |= J.atomic_out != 0;
     table.push_back(J);
   }
   return table;
@@ -112,7 +117,7 @@ bool build_items(xeng_plan* pl) {
   const std::vector<QueueJob> table = job_table(pl);
   uint8_t* image = nullptr;
   size_t bytes = 0;
-  build_queue_image(table.data(), (int)table.size(), pl->split, &image, &bytes, pl->items);
+  build_queue_image(table.data(), (int)table.size(), pl->split, &image, &bytes, &pl->items);
   if (image == nullptr) return false;
   pl->image.assign(image, image + bytes);
   std::free(image);
@@ -133,13 +138,13 @@ xeng_status upload(xeng_plan* pl, void* d_ws, hipStream_t stream) {
 }
 
 xeng_status launch(xeng_plan* pl, void* d_ws, hipStream_t stream) {
-  if (pl->needs_fill) {
+  if (pl->any_atomic) {
     queue_fill_kernel<<<dim3(64, (unsigned)pl->windows.size()), dim3(256), 0, stream>>>(
         reinterpret_cast<const uint8_t*>(d_ws));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return device_error(e, "plan zero fill");
   }
-  hipError_t e = launch_queues(d_ws, pl->items, pl->grid, stream);
+  hipError_t e = launch_queue(d_ws, pl->items, pl->grid, stream);
   return e == hipSuccess ? XENG_OK : device_error(e, "plan queue launch");
 }
 
@@ -169,7 +174,9 @@ xeng_status xeng_plan_create(xeng_plan** out, const xeng_job* jobs, int njobs,
   if (out == nullptr || jobs == nullptr || njobs < 1)
     return fail(XENG_EINVAL, "need an output handle and at least one job");
   *out = nullptr;
-  const int64_t win = wide_max_samples_per_launch();
+  // one window per job: the queue kernel's sums are unscaled, so an item may
+  // cover any sample count the int32 range guard admits
+  const int64_t win = XENG_MAX_SAMPLES;
   auto pl = new (std::nothrow) xeng_plan();
   if (pl == nullptr) return fail(XENG_ENOMEM, "plan allocation failed");
   for (int k = 0; k < njobs; ++k) {
@@ -224,7 +231,7 @@ size_t xeng_plan_workspace_bytes(const xeng_plan* plan) {
 }
 
 int64_t xeng_plan_items(const xeng_plan* plan) {
-  return plan == nullptr ? -1 : plan->items[0] + plan->items[1];
+  return plan == nullptr ? -1 : plan->items;
 }
 
 int xeng_plan_split(const xeng_plan* plan) { return plan == nullptr ? -1 : plan->split; }
@@ -312,6 +319,13 @@ xeng_status xeng_plan_autotune(xeng_plan* plan, void* d_workspace, void* hip_str
                                const char* tune_cache_path, float* best_ms) {
   using namespace xeng;
   if (plan == nullptr || d_workspace == nullptr) return fail(XENG_EINVAL, "null plan or workspace");
+  // Every candidate run writes the jobs' outputs. Timing them on jobs that
+  // add into held sums would add the frame into those sums many times over.
+  for (size_t k = 0; k < plan->jobs.size(); ++k)
+    if (plan->jobs[k].accumulate)
+      return fail(XENG_EINVAL,
+                  "job %zu accumulates: autotune overwrites the outputs, so it needs a plan "
+                  "whose jobs all overwrite (xeng_plan_set_frame with accumulate = 0)", k);
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (reps < 1) reps = 1;
   drop_graph(plan);

@@ -63,7 +63,7 @@ struct Slot {
   std::vector<int64_t> jobs;
   size_t frame_bytes = 0;
   std::vector<uint8_t> image;
-  int64_t items[xeng::kQueueKinds] = {0, 0};   // items of each kind in the image
+  int64_t items = 0;               // items in the image
 };
 
 }  // namespace
@@ -146,17 +146,16 @@ bool build_image(xeng_server* s, Slot& sl, const std::vector<std::pair<int64_t, 
     q.cs = (int64_t)fr.t * J.n;
     q.t0 = 0;
     q.t_end = fr.t;
-    q.nbr = (J.n + 127) / 128;
-    q.ntiles = (int)queue_tiles_per_channel(J.n);
+    q.nbc = (J.n + 255) / 256;
+    q.units = q.nbc * q.nbc;
     q.total_stages = (fr.t + stage - 1) / stage;
     q.accumulate = J.summed ? 1 : 0;
     q.atomic_out = 0;
-    q.full_panels = (J.n % 256) == 0;
     q.zero_first = 0;
   }
   uint8_t* image = nullptr;
   size_t bytes = 0;
-  build_queue_image(table.data(), nw, 1, &image, &bytes, sl.items);
+  build_queue_image(table.data(), nw, 1, &image, &bytes, &sl.items);
   const bool fits = image != nullptr && bytes <= s->slot_bytes;
   if (fits) sl.image.assign(image, image + bytes);
   std::free(image);
@@ -236,10 +235,8 @@ xeng_status xeng_submit(xeng_server* s, int64_t job_id, const uint8_t* d_frame, 
   auto it = s->jobs.find(job_id);
   if (it == s->jobs.end()) return fail(XENG_ENOTFOUND, "unknown job %lld", (long long)job_id);
   ServerJob& J = it->second;
-  if (d_frame == nullptr || (uintptr_t)d_frame % 4 != 0 || t < 1 ||
-      t > xeng::wide_max_samples_per_launch())
-    return fail(XENG_EINVAL, "frame must be non-null, 4-byte aligned, 1 <= t <= %lld",
-                (long long)xeng::wide_max_samples_per_launch());
+  if (d_frame == nullptr || (uintptr_t)d_frame % 4 != 0 || t < 1)
+    return fail(XENG_EINVAL, "frame must be non-null, 4-byte aligned, with t >= 1");
   if (J.held + t > XENG_MAX_SAMPLES)
     return fail(XENG_ERANGE, "job %lld would hold %lld samples, beyond the exact int32 range",
                 (long long)job_id, (long long)(J.held + t));
@@ -288,7 +285,7 @@ xeng_status xeng_server_step(xeng_server* s, int* launched) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(ws, sl.image.data(), sl.image.size(), hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess) e = hipEventRecord(sl.start, sl.stream);
-    if (e == hipSuccess) e = xeng::launch_queues(ws, sl.items, s->grid, sl.stream);
+    if (e == hipSuccess) e = xeng::launch_queue(ws, sl.items, s->grid, sl.stream);
     if (e == hipSuccess) e = hipEventRecord(sl.end, sl.stream);
     if (e != hipSuccess) return device_error(e, "step launch");
     sl.busy = true;

@@ -37,7 +37,13 @@ PATHFINDER = Workload("pathfinder", n=256, f=256, t=16384, sigma=2.5, seed=2, co
 LARGE_N = Workload("large_n", n=2048, f=16, t=65536, sigma=3.0, seed=30, frames=4,
                    frame_seeds=(30, 31, 32, 33))
 
-WORKLOADS = {w.name: w for w in (TINY, PATHFINDER, LARGE_N)}
+# Small arrays are bound by HBM, not by the matrix cores: at N = 64 one input
+# byte carries 4 (N + 1) = 260 effective operations, under the ~625 op/B ridge
+# of the int8 MFMA peak against 8 TB/s. 1024 channels of 16384 samples are
+# 1 GiB of input per frame.
+SMALL_N = Workload("small_n", n=64, f=1024, t=16384, sigma=2.5, seed=6)
+
+WORKLOADS = {w.name: w for w in (TINY, PATHFINDER, LARGE_N, SMALL_N)}
 
 
 def batched_jobs(seed: int = 4, count: int = 64):

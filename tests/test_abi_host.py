@@ -94,13 +94,16 @@ def test_unknown_variant(lib):
 
 
 def test_choose_variant_dispatch_rule():
-    # triangle kernel for aligned n <= 256 with n % 4 == 0; wide kernel for other
-    # aligned n % 4 == 0; the general kernel otherwise
+    # triangle kernel for aligned n <= 256 with n % 4 == 0; diagonal squares and
+    # off-diagonal tiles for other aligned n % 4 == 0; the general kernel otherwise
     import paper_1503_06203_amd as xe
     assert xe.choose_variant(256, 256, 16384)[2].startswith("tri256")
     assert xe.choose_variant(4, 1, 10)[2].startswith("tri256")
-    assert xe.choose_variant(260, 4, 100)[2].startswith("wide128x256_w8")
-    assert xe.choose_variant(2048, 16, 65536)[2].startswith("wide128x256_w8")
+    assert xe.choose_variant(260, 4, 100)[2].startswith("rect128x256")
+    assert xe.choose_variant(2048, 16, 65536)[2].startswith("rect128x256")
+    # the large-N frame (16 channels x 64 pieces) fills 4 whole rounds of the
+    # 256 compute units without splitting the time axis
+    assert xe.choose_variant(2048, 16, 65536)[1] == 1
     assert xe.choose_variant(255, 4, 100)[2].startswith("tile128")
     assert xe.choose_variant(256, 4, 100, aligned=False)[2].startswith("tile128")
     # one channel of a long integration is split in time across workgroups
@@ -145,9 +148,9 @@ def test_plan_host_logic(lib):
         jobs[k] = XengJob(base_in + k * (1 << 28), base_vis + k * (1 << 28), n, f, t, 0, 0)
     h = ctypes.c_void_p()
     assert lib.xeng_plan_create(ctypes.byref(h), jobs, 3, None) == 0
-    # N <= 256 runs on the triangle kernel, one item per channel (2 + 1); N=2048
-    # on 128x256 tiles reaching the upper triangle: 72 per channel
-    assert lib.xeng_plan_items(h) == 2 + 1 + 72
+    # N <= 256 is one diagonal square (the whole triangle) per channel (2 + 1);
+    # N=2048 is 8 squares plus the 56 128x256 tiles above them per channel
+    assert lib.xeng_plan_items(h) == 2 + 1 + 64
     assert lib.xeng_plan_split(h) == 1
     assert lib.xeng_plan_workspace_bytes(h) > 0
     lib.xeng_plan_destroy(h)

@@ -148,9 +148,10 @@ VARIANT_SHAPES = [(1, 64, 4), (2, 97, 128), (1, 200, 256), (2, 333, 260), (1, 10
 TRI_VARIANT = 3
 TRI_BF6_VARIANT = 4
 TRI_VARIANTS = [TRI_VARIANT, TRI_BF6_VARIANT]
+RECT_VARIANT = 5
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("f,t,n", VARIANT_SHAPES)
 def test_each_variant_matches_oracle(variant, f, t, n):
     x = synth.quantized_gaussian(f, t, n, 3.0, seed=f * 7919 + t * 31 + n)
@@ -265,3 +266,72 @@ def test_int32_boundary_on_gpu():
     v2 = xe.new_vis(8, 1, device=DEV)
     with pytest.raises(xe.XengError):
         xe.correlate(x[:, :1].contiguous(), v2, t_prev=t, accumulate=True)
+
+
+# Diagonal squares and off-diagonal tiles (n > 256): element counts around the
+# 128-row and 256-column edges, with partial last squares and tiles.
+@pytest.mark.parametrize("n", [260, 264, 380, 384, 388, 508, 512, 516, 636, 640, 768, 772, 1020,
+                               1024, 1028])
+def test_rect_element_counts(n):
+    x = synth.quantized_gaussian(2, 301, n, 3.0, seed=3000 + n)
+    full_check(x, variant=RECT_VARIANT, split=1)
+
+
+@pytest.mark.parametrize("t", [1, 7, 63, 64, 65, 127, 128, 129, 191, 192, 193, 257, 1000])
+def test_rect_sample_counts(t):
+    x = synth.quantized_gaussian(1, t, 512, 2.5, seed=4000 + t)
+    full_check(x, variant=RECT_VARIANT, split=1)
+
+
+@pytest.mark.parametrize("split", [2, 3, 5, 16])
+@pytest.mark.parametrize("t", [200, 1000, 4097])
+def test_rect_time_split(split, t):
+    x = synth.quantized_gaussian(2, t, 516, 2.5, seed=split * 37 + t)
+    xd = x.to(DEV)
+    ref = gpu_correlate(xd, variant=0, split=1)
+    got = gpu_correlate(xd, variant=RECT_VARIANT, split=split)
+    assert torch.equal(ref, got)
+    assert_same(got, oracle.correlate(x.numpy()))
+    prev = torch.randint(-1000, 1000, ref.shape, dtype=torch.int32, device=DEV)
+    got2 = gpu_correlate(xd, variant=RECT_VARIANT, split=split, prev=prev.clone(), t_prev=10)
+    assert torch.equal(got2, ref + prev)
+
+
+def test_rect_accumulate_and_many_channels():
+    x = synth.quantized_gaussian(40, 130, 300, 2.5, seed=71)
+    xd = x.to(DEV)
+    first = gpu_correlate(xd[:, :70].contiguous(), variant=RECT_VARIANT)
+    both = gpu_correlate(xd[:, 70:].contiguous(), variant=RECT_VARIANT, prev=first, t_prev=70)
+    assert_same(both, oracle.correlate(x.numpy()))
+
+
+def test_rect_offset_sums_wrap_exactly():
+    # every byte 0xFF over the longest allowed integration in one workgroup:
+    # the uncorrected field products of a square and of a tile wrap int32, the
+    # corrected result (98 per sample) does not
+    import paper_1503_06203_amd as xe
+    t = xe.MAX_SAMPLES
+    x = synth.constant_bytes(1, t, 264, 0xFF, device=DEV)
+    vis = gpu_correlate(x, variant=RECT_VARIANT, split=1).cpu().numpy()
+    assert (vis[..., 0] == 98 * t).all() and (vis[..., 1] == 0).all()
+
+
+def test_rect_constant_extremes_exercise_masking():
+    # 0x00 decodes to (-8,-8): a padded sample or element read as 0x00 instead
+    # of a zero field would add 128 per entry
+    for t in (1, 65, 200):
+        x = synth.constant_bytes(2, t, 520, 0x00, device=DEV)
+        vis = gpu_correlate(x, variant=RECT_VARIANT).cpu().numpy()
+        assert (vis[..., 0] == 128 * t).all() and (vis[..., 1] == 0).all()
+
+
+def test_large_n_one_channel_in_full():
+    # one channel of a large-N frame (N=2048, T=65536, sigma 3), every entry
+    # against the oracle: 1.4e11 complex multiply-adds on the host
+    w = workloads.LARGE_N
+    xd = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, w.seeds()[0], device=DEV)
+    vis = gpu_correlate(xd)
+    ch = w.f - 1
+    x = xd[ch:ch + 1].cpu().numpy()
+    del xd
+    assert_same(vis[ch:ch + 1], oracle.correlate(x), "channel %d" % ch)

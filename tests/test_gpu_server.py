@@ -61,6 +61,60 @@ def test_alone_equals_mix():
     srv.close()
 
 
+def test_served_shapes_alone_equals_mix_and_oracle():
+    # The served workload's job shapes: N in {256, 2048, 8192}, F in {1, 2, 8},
+    # T = 16384 per frame, sigma 2.5. Frames of every job are interleaved and
+    # served with continuous batching; each job's sums must equal its frames
+    # run alone (tolerance 0) and the oracle: in full for an N=256 job and one
+    # channel of an N=2048 job, and for the N=8192, F=1 job on every pair of a
+    # tile-boundary element subset plus five whole rows.
+    from gpu_helpers import boundary_elements, gather_subset
+    t = 16384
+    jobs = {"a": (256, 8, 3), "b": (2048, 2, 2), "c": (8192, 1, 2), "d": (8192, 8, 1),
+            "e": (2048, 8, 1), "f": (256, 1, 2)}
+    frames = {k: [synth.quantized_gaussian(f, t, n, 2.5, seed=500 + 10 * i + j, device=DEV)
+                  for j in range(nf)]
+              for i, (k, (n, f, nf)) in enumerate(jobs.items())}
+    srv = xe.Server(hbm_budget=64 << 30, max_inflight=2)
+    acc = {k: xe.new_vis(n, f, device=DEV) for k, (n, f, _) in jobs.items()}
+    ids = {k: srv.open_job(jobs[k][0], jobs[k][1], acc[k]) for k in jobs}
+    order = [(k, j) for j in range(3) for k in jobs if j < jobs[k][2]]
+    tickets = []
+    for i, (k, j) in enumerate(order):
+        tickets.append(srv.submit(ids[k], frames[k][j]))
+        if i % 2 == 1:
+            srv.step()
+    srv.drain()
+    for tk in tickets:
+        done, lat = srv.poll(tk)
+        assert done and lat >= 0.0
+    for k in jobs:
+        assert torch.equal(acc[k], alone(frames[k])), k
+    # N=256, F=8: every entry of every channel
+    xa = torch.cat(frames["a"], dim=1).cpu().numpy()
+    assert np.array_equal(acc["a"].cpu().numpy().astype(np.int64), oracle.correlate(xa))
+    # N=2048, F=2: every entry of channel 1
+    xb = torch.cat([x[1:2] for x in frames["b"]], dim=1).cpu().numpy()
+    assert np.array_equal(acc["b"][1:2].cpu().numpy().astype(np.int64), oracle.correlate(xb))
+    # N=8192, F=1: all pairs among elements around every 128/256 edge
+    n = 8192
+    xc = torch.cat(frames["c"], dim=1)
+    elems = boundary_elements(n, tile=128, extra=16, offsets=(-1, 0))
+    sub = xc[:, :, torch.as_tensor(elems, device=DEV)].cpu().numpy()
+    assert np.array_equal(gather_subset(acc["c"], n, elems), oracle.correlate(sub))
+    # ... and whole rows i (every j >= i)
+    xcc = xc.cpu().numpy()
+    for i in (0, 255, 256, 4095, n - 129):
+        j = np.arange(i, n)
+        fij = np.stack([np.zeros_like(j), np.full_like(j, i), j], axis=1)
+        k0 = i * (2 * n - i + 1) // 2
+        got = acc["c"][0, k0:k0 + len(j)].cpu().numpy().astype(np.int64)
+        assert np.array_equal(got, oracle.entries(xcc, fij)), i
+    for k in jobs:
+        srv.close_job(ids[k])
+    srv.close()
+
+
 def test_admission_and_backpressure():
     n, f = 256, 2
     acc_bytes = f * n * (n + 1) // 2 * 8

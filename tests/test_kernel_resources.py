@@ -41,7 +41,7 @@ def test_triangle_kernel_has_no_scratch_and_fits_lds(tmp_path):
                    "xcorr_tri_segments_kernel"):
         assert kernel_field(asm, kernel, "amdhsa_private_segment_fixed_size") == 0
     for kernel in ("xcorr_tri_kernel", "xcorr_tri_delay_kernel", "xcorr_tri_window_kernel",
-                   "xcorr_tri_queue_kernel"):
+                   "xcorr_tri_segments_kernel"):
         assert kernel_field(asm, kernel, "amdhsa_group_segment_fixed_size") <= 160 * 1024
 
 
@@ -51,3 +51,14 @@ def test_bf6_triangle_kernel_has_no_scratch_and_fits_lds(tmp_path):
     asm = device_asm("xcorr_tri_bf6.hip", tmp_path)
     assert kernel_field(asm, "xcorr_tri_bf6_kernel", "amdhsa_private_segment_fixed_size") == 0
     assert kernel_field(asm, "xcorr_tri_bf6_kernel", "amdhsa_group_segment_fixed_size") <= 160 * 1024
+
+
+def test_rect_kernel_has_no_scratch_and_fits_lds(tmp_path):
+    # the kernel for n > 256 (diagonal squares and off-diagonal tiles): two
+    # waves per SIMD with 128-160 accumulators each; a spill would put scratch
+    # traffic into the vector-memory queue that the staging waits count on
+    # (and its persistent queue form, which runs the same pieces per queue item)
+    asm = device_asm("xcorr_rect.hip", tmp_path)
+    for kernel in ("xcorr_rect_kernel", "xcorr_queue_kernel"):
+        assert kernel_field(asm, kernel, "amdhsa_private_segment_fixed_size") == 0, kernel
+        assert kernel_field(asm, kernel, "amdhsa_group_segment_fixed_size") <= 160 * 1024, kernel
