@@ -406,29 +406,91 @@ def bench_batched(steps: int, warmup: int):
     }
 
 
-def bench_served(rate_hz: float = 2000.0, frames: int = 300):
-    """Poisson stream of frames through the continuous-batching server."""
+def bench_served(rate_hz: float = 2000.0, frames: int = 2000):
+    """Poisson streams of frames through the continuous-batching server.
+
+    The frame mix is N in {256, 2048, 8192} with weights 0.6 / 0.35 / 0.05, F
+    uniform in {1, 2, 8}, T = 16384. The HBM budget holds every job's
+    accumulator plus 1.5 GiB of frames in flight, so admission defers frames
+    when large ones pile up. Runs: the stream at rate_hz (the headline), the
+    same frames all at once (closed-loop capacity), a sweep of rates at 25 to
+    90 % of that capacity, a uniform mix at rate_hz (overload: about twice
+    the capacity is offered), and the same frames as plain per-job launches
+    in arrival order (the comparison for aggregate throughput)."""
+    import numpy as np
     import torch
 
+    import paper_1503_06203_amd as xe
     import synth
-    from paper_1503_06203_amd import serve
+    from paper_1503_06203_amd import metrics, serve
     from synth import workloads
 
-    arrivals, ns, fs, t = workloads.served_stream(rate_hz=rate_hz, frames=frames)
-    gen_seed = [0]
+    pools = {}
 
     def frames_for(n, f):
-        gen_seed[0] += 1
-        return [synth.quantized_gaussian(f, t, n, 2.5, seed=5000 + gen_seed[0] * 10 + k,
-                                         device="cuda:0") for k in range(2)]
+        if (n, f) not in pools:
+            pools[(n, f)] = [synth.quantized_gaussian(f, 16384, n, 2.5,
+                                                      seed=5000 + 100 * n + 10 * f + k,
+                                                      device="cuda:0") for k in range(2)]
+        return pools[(n, f)]
 
-    stats, acc = serve.run_stream(arrivals, ns, fs, t, frames_for, hbm_budget=200 << 30,
-                                  max_inflight=2)
-    del acc
+    acc_bytes = sum(metrics.output_bytes(n, f) for n in (256, 2048, 8192) for f in (1, 2, 8))
+    budget = acc_bytes + (3 << 29)
+
+    def run(arr, ns, fs):
+        stats, acc = serve.run_stream(arr, ns, fs, t, frames_for, hbm_budget=budget,
+                                      max_inflight=2)
+        del acc
+        return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()}
+
+    arrivals, ns, fs, t = workloads.served_stream(rate_hz=rate_hz, frames=frames)
+    out = run(arrivals, ns, fs)
+    out.update({"workload": "served", "rate_hz": rate_hz,
+                "mix": "N in {256, 2048, 8192} weights 0.6/0.35/0.05, F uniform in {1, 2, 8}, "
+                       "T=16384"})
+    closed = run(np.zeros_like(arrivals), ns, fs)
+    cap = closed["frames_per_s"]
+    out["closed_loop"] = {"frames_per_s": cap, "throughput_tops": closed["throughput_tops"],
+                          "p50_latency_ms": closed["p50_latency_ms"],
+                          "p99_latency_ms": closed["p99_latency_ms"]}
+    sweep = []
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        a, n2, f2, _ = workloads.served_stream(rate_hz=frac * cap, frames=frames // 2, seed=6)
+        r = run(a, n2, f2)
+        sweep.append({"load": frac, "offered_rate_hz": r["offered_rate_hz"],
+                      "throughput_tops": r["throughput_tops"], "frames_per_s": r["frames_per_s"],
+                      "p50_latency_ms": r["p50_latency_ms"], "p99_latency_ms": r["p99_latency_ms"]})
+    out["rate_sweep"] = sweep
+    a, n3, f3, _ = workloads.served_stream(rate_hz=rate_hz, frames=frames // 4, seed=7,
+                                           n_weights=(1.0, 1.0, 1.0))
+    over = run(a, n3, f3)
+    out["overload_uniform_mix"] = {k: over[k] for k in (
+        "frames", "completed", "offered_rate_hz", "throughput_tops", "frames_per_s",
+        "p50_latency_ms", "p99_latency_ms", "peak_bytes_in_use", "peak_pending_frames")}
+    # the same frames, one plain call per frame in arrival order (each job's
+    # frames add into its own accumulator), closed loop
+    accs = {}
+    for n, f in sorted({(int(a), int(b)) for a, b in zip(ns, fs)}):
+        accs[(n, f)] = xe.new_vis(n, f, device="cuda:0")
+    use = {k: 0 for k in accs}
+    calls = []
+    for n, f in zip(ns, fs):
+        k = (int(n), int(f))
+        calls.append((frames_for(*k)[use[k] % 2], accs[k], use[k] * t))
+        use[k] += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for x, v, held in calls:
+        xe.correlate(x, v, accumulate=held > 0, t_prev=held)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ops = sum(metrics.effective_ops(int(n), int(f), t) for n, f in zip(ns, fs))
+    out["per_job_plain"] = {"throughput_tops": round(ops / wall / 1e12, 3),
+                            "frames_per_s": round(len(calls) / wall, 1)}
+    out["served_vs_per_job"] = round(closed["throughput_tops"] / (ops / wall / 1e12), 3)
+    del pools, accs, calls
     torch.cuda.empty_cache()
-    stats["workload"] = "served"
-    stats["rate_hz"] = rate_hz
-    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()}
+    return out
 
 
 def main():

@@ -105,6 +105,11 @@ xeng_status xeng_correlate(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
  *     triangle cut into 256-element diagonal squares (the blocks of variant 3)
  *     and 128 x 256 tiles wholly above them (Sec. II-C: only tiles that reach
  *     the upper triangle are computed); the default for n > 256.
+ *   6 small64_w8_ring16_mfma32x32x32   n <= 64, n % 4 == 0, aligned input: each
+ *     wave streams one channel (or a part of its time axis) through a private
+ *     ring in LDS; bound by HBM rather than the matrix cores at these sizes;
+ *     the default for n <= 64. split_t is ignored (the kernel combines its
+ *     time parts itself).
  */
 int xeng_variant_count(void);
 const char* xeng_variant_name(int variant);   /* NULL if out of range */
@@ -177,8 +182,9 @@ xeng_status xeng_correlate_delayed(const uint8_t* d_in, int32_t* d_vis, int n, i
 /*
  * The variant and time split xeng_correlate would use for a job of this shape
  * (host only, no device work). input_aligned: the input pointer is 4-byte
- * aligned. Kernels: tri256 (n <= 256, n % 4 == 0, aligned input: one workgroup
- * per channel covers the whole triangle), rect128x256_tri256 (other aligned
+ * aligned. Kernels: small64 (n <= 64, n % 4 == 0, aligned input: a wave per
+ * channel or part of one), tri256 (n <= 256 likewise: one workgroup per
+ * channel covers the whole triangle), rect128x256_tri256 (other aligned
  * n % 4 == 0 jobs), tile128 (everything else). Returns XENG_EINVAL for n < 1, f < 1
  * or t < 0, or a NULL output pointer.
  */

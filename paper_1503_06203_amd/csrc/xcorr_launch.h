@@ -43,6 +43,16 @@ hipError_t launch_rect(const uint8_t* in, int32_t* vis, int n, int f, int t, int
                        hipStream_t stream);
 int64_t rect_units_per_channel(int n);
 
+// Kernel for arrays of at most small_max_elements() elements (n % 4 == 0,
+// 4-byte aligned input), bound by the input stream: each wave correlates one
+// channel over a part of the time axis from a private ring of staged samples.
+// Sums samples [t0, t0 + t_count) of each channel (any t_count); cus = compute
+// units to fill. Overwrites vis unless accumulate (no zero fill needed).
+hipError_t launch_small(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                        int64_t cs, int t0, int t_count, int accumulate, int cus,
+                        hipStream_t stream);
+int small_max_elements();
+
 // Triangle kernel for n <= tri_max_elements() (n % 4 == 0, 4-byte aligned
 // input): one workgroup per channel (times split) computes the channel's whole
 // upper triangle. Sums samples [t0, t0 + t_count) of each channel; sums are

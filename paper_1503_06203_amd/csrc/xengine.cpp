@@ -100,6 +100,7 @@ const Variant kVariants[] = {
     {"tri256_w8_kc64_mfma32x32x32"},      // n <= 256, n % 4 == 0, 4-byte aligned input
     {"tri256_w8_bf6_mfma32x32x64"},       // as above, on bf6 operands (exact)
     {"rect128x256_tri256_w8_kc64_mfma32x32x32"},  // n % 4 == 0, 4-byte aligned input
+    {"small64_w8_ring16_mfma32x32x32"},   // n <= 64, n % 4 == 0, 4-byte aligned input
 };
 constexpr int kVariantTile128 = 0;
 constexpr int kVariantWide = 1;
@@ -107,6 +108,7 @@ constexpr int kVariantWide8 = 2;
 constexpr int kVariantTri = 3;
 constexpr int kVariantTriBf6 = 4;
 constexpr int kVariantRect = 5;
+constexpr int kVariantSmall = 6;
 constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // The kernel xeng_correlate uses: the triangle kernel where it applies (it
@@ -114,6 +116,7 @@ constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
 // squares and off-diagonal tiles for dword-loadable inputs, else the general
 // one.
 int default_variant(int n, bool aligned) {
+  if (aligned && n <= xeng::small_max_elements()) return kVariantSmall;
   if (aligned && n <= xeng::tri_max_elements()) return kVariantTri;
   return aligned ? kVariantRect : kVariantTile128;
 }
@@ -234,6 +237,10 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
   if (rect && !aligned)
     return fail(XENG_EINVAL, "variant %s needs n %% 4 == 0 and a 4-byte aligned input",
                 kVariants[variant].name);
+  const bool small = variant == kVariantSmall;
+  if (small && !(aligned && n <= xeng::small_max_elements()))
+    return fail(XENG_EINVAL, "variant %s needs n <= %d, n %% 4 == 0 and a 4-byte aligned input",
+                kVariants[variant].name, xeng::small_max_elements());
   const bool tri = variant == kVariantTri || variant == kVariantTriBf6;
   if (tri && !tri_ok)
     return fail(XENG_EINVAL, "variant %s needs n <= %d, n %% 4 == 0 and a 4-byte aligned input",
@@ -245,12 +252,17 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
   if (variant == kVariantWide8 && split_t == 0)
     split = xeng::wide_auto_split(n, f, t, xeng::device_cu_count());
   if (rect && split_t == 0) split = xeng::rect_auto_split(n, f, t, xeng::device_cu_count());
+  // the small kernel combines its time parts itself: no split, no fill
+  if (small) split = 1;
   if (split > 1 && !accumulate) {
     hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
     if (e != hipSuccess) return device_error(e, "zero fill");
   }
   hipError_t e = hipSuccess;
-  if (variant == kVariantTri) {
+  if (small) {
+    e = xeng::launch_small(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate,
+                           xeng::device_cu_count(), stream);
+  } else if (variant == kVariantTri) {
     e = xeng::launch_tri(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
   } else if (rect) {
     e = xeng::launch_rect(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);

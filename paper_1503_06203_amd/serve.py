@@ -44,6 +44,8 @@ def run_stream(arrival_s, ns, fs, t: int, frames_for, hbm_budget: int, max_infli
     use = {s: 0 for s in shapes}
     i = 0
     done = 0
+    peak_bytes = 0
+    peak_pending = 0
     t0 = time.perf_counter()
     while done < total:
         now = time.perf_counter() - t0
@@ -57,6 +59,9 @@ def run_stream(arrival_s, ns, fs, t: int, frames_for, hbm_budget: int, max_infli
             pending.append(i)
             i += 1
         srv.step()
+        st = srv.stats()
+        peak_bytes = max(peak_bytes, st["bytes_in_use"])
+        peak_pending = max(peak_pending, st["pending_frames"])
         still = []
         for k in pending:
             ok, l_us = srv.poll(tickets[k])
@@ -85,6 +90,9 @@ def run_stream(arrival_s, ns, fs, t: int, frames_for, hbm_budget: int, max_infli
         "p50_latency_ms": float(np.percentile(served, 50) / 1e3) if served.size else None,
         "p99_latency_ms": float(np.percentile(served, 99) / 1e3) if served.size else None,
         "max_latency_ms": float(served.max() / 1e3) if served.size else None,
+        "hbm_budget_bytes": int(hbm_budget),
+        "peak_bytes_in_use": int(peak_bytes),
+        "peak_pending_frames": int(peak_pending),
     }
     srv.close()
     return stats, acc

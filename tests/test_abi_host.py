@@ -94,11 +94,15 @@ def test_unknown_variant(lib):
 
 
 def test_choose_variant_dispatch_rule():
-    # triangle kernel for aligned n <= 256 with n % 4 == 0; diagonal squares and
+    # small kernel for aligned n <= 64, triangle kernel for aligned n <= 256
+    # with n % 4 == 0; diagonal squares and
     # off-diagonal tiles for other aligned n % 4 == 0; the general kernel otherwise
     import paper_1503_06203_amd as xe
     assert xe.choose_variant(256, 256, 16384)[2].startswith("tri256")
-    assert xe.choose_variant(4, 1, 10)[2].startswith("tri256")
+    assert xe.choose_variant(68, 1, 10)[2].startswith("tri256")
+    # arrays of at most 64 elements stream through the small kernel
+    assert xe.choose_variant(4, 1, 10)[2].startswith("small64")
+    assert xe.choose_variant(64, 1024, 16384)[2].startswith("small64")
     assert xe.choose_variant(260, 4, 100)[2].startswith("rect128x256")
     assert xe.choose_variant(2048, 16, 65536)[2].startswith("rect128x256")
     # the large-N frame (16 channels x 64 pieces) fills 4 whole rounds of the

@@ -123,10 +123,79 @@ def test_batched_workload_matches_per_job():
     torch.cuda.synchronize()
     for k, (x, vis) in enumerate(jobs):
         assert torch.equal(vis, plain(x)), k
-    from gpu_helpers import boundary_elements, gather_subset, subset_reference, assert_same
-    for k in (0, 17, 63):
-        x, vis = jobs[k]
+    # every job against the oracle: all pairs among the elements on both sides
+    # of every 128-element edge (every piece boundary) plus a few random ones
+    from gpu_helpers import boundary_elements, gather_subset, assert_same
+    for k, (x, vis) in enumerate(jobs):
         n = x.shape[2]
-        elems = boundary_elements(n, extra=4, offsets=(-1, 0))
+        elems = boundary_elements(n, extra=4, seed=k, offsets=(-1, 0))
         sub = x[:, :, torch.as_tensor(elems, device=DEV)].cpu().numpy()
         assert_same(gather_subset(vis, n, elems), oracle.correlate(sub), "job %d" % k)
+
+
+def test_graph_captured_accumulating_then_overwriting():
+    # A plan whose items are split in time combines partial sums with atomic
+    # adds, after a zero fill when a job overwrites. Captured while the jobs
+    # accumulate, the graph must still zero-fill once set_frame switches them
+    # to overwriting (the fill kernel reads each job's flag on the device).
+    shapes = [(256, 2, 2048), (512, 1, 1500)]
+    jobs = make_jobs(shapes, seed=7)
+    plan = xe.Plan(jobs)
+    plan.autotune(reps=1)                      # overwriting jobs: allowed
+    frame1 = [synth.quantized_gaussian(x.shape[0], x.shape[1], x.shape[2], 2.5, seed=70 + k,
+                                       device=DEV) for k, (x, _) in enumerate(jobs)]
+    plan.set_frame(frame1, accumulate=True)
+    if plan.split == 1:
+        pytest.skip("autotuner chose no time split on this device")
+    plan.capture_graph()
+    plan.replay()                              # frame 0 + frame 1
+    torch.cuda.synchronize()
+    plan.set_frame(frame1, accumulate=False)   # overwrite with frame 1 alone
+    for rep in range(3):
+        for (_, v) in jobs:
+            v.fill_(-12345)                    # stale sums the fill must clear
+        plan.replay()
+        torch.cuda.synchronize()
+        for k, (_, v) in enumerate(jobs):
+            want = oracle.correlate(frame1[k].cpu().numpy())
+            assert np.array_equal(v.cpu().numpy().astype(np.int64), want), (rep, k)
+
+
+def test_forced_split_graph_zero_fill(tmp_path):
+    # the same with a tuned split of 4 read from a cache file (no autotune run)
+    shapes = [(256, 2, 2048), (512, 1, 1500)]
+    jobs = make_jobs(shapes, seed=8)
+    key = "plan" + "".join(":%dx%dx%d" % (x.shape[2], x.shape[0], x.shape[1]) for x, _ in jobs)
+    cache = tmp_path / "tune.txt"
+    cache.write_text(key + " 4\n")
+    plan = xe.Plan(jobs, tune_cache=cache)
+    assert plan.split == 4
+    plan.set_frame(None, accumulate=True)
+    plan.capture_graph()
+    plan.set_frame(None, accumulate=False)
+    for (_, v) in jobs:
+        v.fill_(777)
+    plan.replay()
+    torch.cuda.synchronize()
+    for (x, v) in jobs:
+        assert np.array_equal(v.cpu().numpy().astype(np.int64), oracle.correlate(x.cpu().numpy()))
+
+
+def test_autotune_refuses_accumulating_plan():
+    shapes = [(256, 2, 512), (64, 1, 300)]
+    jobs = make_jobs(shapes, seed=9)
+    plan = xe.Plan(jobs)
+    plan.run()
+    torch.cuda.synchronize()
+    before = [v.clone() for _, v in jobs]
+    plan.set_frame(None, accumulate=True)
+    with pytest.raises(xe.XengError) as e:
+        plan.autotune(reps=2)
+    assert e.value.status == -1
+    torch.cuda.synchronize()
+    for b, (_, v) in zip(before, jobs):
+        assert torch.equal(b, v)               # nothing ran
+    plan.run()                                 # the accumulating frame, once
+    torch.cuda.synchronize()
+    for b, (x, v) in zip(before, jobs):
+        assert torch.equal(v, plain(x, prev=b, t_prev=x.shape[1]))

@@ -149,13 +149,14 @@ TRI_VARIANT = 3
 TRI_BF6_VARIANT = 4
 TRI_VARIANTS = [TRI_VARIANT, TRI_BF6_VARIANT]
 RECT_VARIANT = 5
+SMALL_VARIANT = 6
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("f,t,n", VARIANT_SHAPES)
 def test_each_variant_matches_oracle(variant, f, t, n):
     x = synth.quantized_gaussian(f, t, n, 3.0, seed=f * 7919 + t * 31 + n)
-    if variant in TRI_VARIANTS and n > 256:
+    if (variant in TRI_VARIANTS and n > 256) or (variant == SMALL_VARIANT and n > 64):
         import paper_1503_06203_amd as xe
         with pytest.raises(xe.XengError):
             gpu_correlate(x.to(DEV), variant=variant, split=1)
@@ -335,3 +336,59 @@ def test_large_n_one_channel_in_full():
     x = xd[ch:ch + 1].cpu().numpy()
     del xd
     assert_same(vis[ch:ch + 1], oracle.correlate(x), "channel %d" % ch)
+
+
+# Small kernel (n <= 64): element counts over the 32-block edge, sample counts
+# around the 16-sample steps and the time parts, channel counts around the
+# packing of channels into workgroups (all parts of a channel in one).
+@pytest.mark.parametrize("n", [4, 8, 12, 28, 32, 36, 60, 64])
+@pytest.mark.parametrize("t", [1, 15, 16, 17, 255, 257, 4097])
+def test_small_element_and_sample_counts(n, t):
+    x = synth.quantized_gaussian(2, t, n, 3.0, seed=5000 + 97 * n + t)
+    full_check(x, variant=SMALL_VARIANT)
+
+
+@pytest.mark.parametrize("f", [1, 3, 255, 256, 257, 700, 1025])
+def test_small_channel_counts(f):
+    x = synth.quantized_gaussian(f, 200, 64, 2.5, seed=6000 + f)
+    full_check(x, variant=SMALL_VARIANT)
+
+
+def test_small_accumulate():
+    x = synth.quantized_gaussian(5, 3000, 48, 2.5, seed=81)
+    xd = x.to(DEV)
+    first = gpu_correlate(xd[:, :1300].contiguous(), variant=SMALL_VARIANT)
+    both = gpu_correlate(xd[:, 1300:].contiguous(), variant=SMALL_VARIANT, prev=first,
+                         t_prev=1300)
+    assert_same(both, oracle.correlate(x.numpy()))
+
+
+def test_small_offset_sums_wrap_exactly():
+    # one channel split over the 8 waves of a workgroup: each part's
+    # uncorrected field products wrap int32; the parts combine modulo 2^32
+    import paper_1503_06203_amd as xe
+    t = xe.MAX_SAMPLES
+    x = synth.constant_bytes(1, t, 64, 0xFF, device=DEV)
+    vis = gpu_correlate(x, variant=SMALL_VARIANT).cpu().numpy()
+    assert (vis[..., 0] == 98 * t).all() and (vis[..., 1] == 0).all()
+
+
+def test_small_constant_extremes_exercise_masking():
+    for n in (60, 64, 20):
+        for t in (1, 17, 200):
+            x = synth.constant_bytes(3, t, n, 0x00, device=DEV)
+            vis = gpu_correlate(x, variant=SMALL_VARIANT).cpu().numpy()
+            assert (vis[..., 0] == 128 * t).all() and (vis[..., 1] == 0).all(), (n, t)
+
+
+def test_small_n_workload_full_size():
+    # N=64, F=1024, T=16384: every channel's entries against the oracle on a
+    # channel sample, plus all channels of a 3-element subset
+    w = workloads.SMALL_N
+    xd = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, w.seed, device=DEV)
+    vis = gpu_correlate(xd)
+    for ch in (0, 511, w.f - 1):
+        assert_same(vis[ch:ch + 1], oracle.correlate(xd[ch:ch + 1].cpu().numpy()), "ch %d" % ch)
+    elems = np.array([0, 31, 63])
+    sub = xd[:, :, torch.as_tensor(elems, device=DEV)].cpu().numpy()
+    assert_same(gather_subset(vis, w.n, elems), oracle.correlate(sub), "subset")

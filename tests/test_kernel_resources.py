@@ -62,3 +62,11 @@ def test_rect_kernel_has_no_scratch_and_fits_lds(tmp_path):
     for kernel in ("xcorr_rect_kernel", "xcorr_queue_kernel"):
         assert kernel_field(asm, kernel, "amdhsa_private_segment_fixed_size") == 0, kernel
         assert kernel_field(asm, kernel, "amdhsa_group_segment_fixed_size") <= 160 * 1024, kernel
+
+
+def test_small_kernel_has_no_scratch_and_fits_lds(tmp_path):
+    # each wave waits on a count of its own outstanding loads; scratch
+    # traffic would join that queue
+    asm = device_asm("xcorr_small.hip", tmp_path)
+    assert kernel_field(asm, "xcorr_small_kernel", "amdhsa_private_segment_fixed_size") == 0
+    assert kernel_field(asm, "xcorr_small_kernel", "amdhsa_group_segment_fixed_size") <= 160 * 1024
