@@ -183,9 +183,15 @@ def bench_gated(w, steps: int, warmup: int):
     ops = metrics.effective_ops(w.n, w.f, w.t)
     del x, vis
     torch.cuda.empty_cache()
-    return {"gates": 2, "block_samples": block, "schedule": "gate 0 one block in four, else gate 1",
-            "runs_per_step": int(np.count_nonzero(np.diff(sched)) + 1),
-            "launches_per_step": 2 if w.n <= 256 else int(np.count_nonzero(np.diff(sched)) + 1),
+    runs = [0, 0]
+    for k in range(nb):
+        if k == 0 or sched[k] != sched[k - 1]:
+            runs[int(sched[k])] += 1
+    # all runs of one gate go to one launch (up to 32 runs per launch)
+    launches = sum((r + 31) // 32 for r in runs)
+    return {"workload": w.name, "n": w.n, "f": w.f, "t": w.t,
+            "gates": 2, "block_samples": block, "schedule": "gate 0 one block in four, else gate 1",
+            "runs_per_step": sum(runs), "launches_per_step": launches,
             "value": round(ops / (wall / steps) / 1e12, 3), "unit": "TOPS",
             "ms_per_step": round(wall / steps * 1e3, 5)}
 
@@ -212,18 +218,27 @@ def bench_delayed(w, steps: int, warmup: int):
     delays[0] = dmax
     vis = xe.new_vis(w.n, w.f)
     ops = metrics.effective_ops(w.n, w.f, w.t)
-    out = {"max_delay": dmax, "delays": "uniform integers in [0, %d]" % dmax}
-    wall, per = time_steps(lambda: xe.correlate_delayed(x, vis, delays), steps, warmup)
+    need = int(xe.lib().xeng_delayed_workspace_bytes(w.n, w.f, w.t))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0") if need else None
+    out = {"workload": w.name, "n": w.n, "f": w.f, "t": w.t, "max_delay": dmax,
+           "delays": "uniform integers in [0, %d]" % dmax,
+           "form": "shift into a %d-byte workspace, then correlate" % need if need
+           else "fused into the triangle kernel's staging"}
+    wall, per = time_steps(lambda: xe.correlate_delayed(x, vis, delays, workspace=ws), steps,
+                           warmup)
     out.update({"value": round(ops / (wall / steps) / 1e12, 3), "unit": "TOPS",
                 "ms_per_step": round(wall / steps * 1e3, 5)})
     same = np.full(w.n, dmax, dtype=np.int32)     # the same input, no relative shift
-    wall0, _ = time_steps(lambda: xe.correlate_delayed(x, vis, same), steps, warmup)
+    wall0, _ = time_steps(lambda: xe.correlate_delayed(x, vis, same, workspace=ws), steps, warmup)
     out["equal_delays_value"] = round(ops / (wall0 / steps) / 1e12, 3)
     near = np.full(w.n, dmax, dtype=np.int32)
-    near[1::2] = dmax - 1                         # spread 1: window form
-    wall1, _ = time_steps(lambda: xe.correlate_delayed(x, vis, near), steps, warmup)
+    near[1::2] = dmax - 1                         # spread 1
+    wall1, _ = time_steps(lambda: xe.correlate_delayed(x, vis, near, workspace=ws), steps, warmup)
     out["spread1_value"] = round(ops / (wall1 / steps) / 1e12, 3)
-    del x, vis
+    plain = xe.new_vis(w.n, w.f)
+    wall2, _ = time_steps(lambda: xe.correlate(x[:, dmax:], plain), steps, warmup)
+    out["no_delays_plain_value"] = round(ops / (wall2 / steps) / 1e12, 3)
+    del x, vis, ws, plain
     torch.cuda.empty_cache()
     return out
 
@@ -568,6 +583,8 @@ def main():
         line["time_major"] = bench_time_major(pw, 20, 3)
         line["gated"] = bench_gated(pw, 10, 2)
         line["delayed"] = bench_delayed(pw, 10, 2)
+        line["large_n_gated"] = bench_gated(w, 5, 1)
+        line["large_n_delayed"] = bench_delayed(w, 5, 1)
         line["bf6"] = bench_bf6(pw, 20, 3)
         line["batched"] = bench_batched(10, 2)
         line["served"] = bench_served()

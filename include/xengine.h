@@ -147,10 +147,11 @@ xeng_status xeng_correlate_strided(const uint8_t* d_in, int64_t sample_stride,
  *   accumulate 0 overwrites every gate's set (gates without samples become
  *          zero), 1 adds to them; each gate's total must stay within
  *          XENG_MAX_SAMPLES (XENG_ERANGE otherwise).
- * For n <= 256 all runs of one gate (consecutive blocks of that gate) are
- * summed in one launch per gate (up to 32 runs each); for larger n each run
- * is one launch. Runs are read in place as sub-ranges, so n % 4 == 0 and a
- * 4-byte aligned d_in are required. Errors as for xeng_correlate, XENG_EINVAL for gates < 1 or > 255,
+ * All runs of one gate (consecutive blocks of that gate) are summed in one
+ * launch per gate (up to 32 runs each), on the triangle kernel for n <= 256
+ * and on the kernel of diagonal squares and tiles above that. Runs are read
+ * in place as sub-ranges, so n % 4 == 0 and a 4-byte aligned d_in are
+ * required. Errors as for xeng_correlate, XENG_EINVAL for gates < 1 or > 255,
  * block < 1, or a gate index out of range.
  */
 xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates, int n, int f,
@@ -173,11 +174,34 @@ xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates,
  * correlation of a shifted sample window, and a delay spread of at most 128
  * samples stages whole rows; otherwise each element's samples are gathered
  * bytewise (slower, any alignment). Errors as for xeng_correlate; XENG_EINVAL
- * for a delay out of range or t % 64 != 0.
+ * for a delay out of range, n > 256 or t % 64 != 0 (xeng_correlate_delayed_ws
+ * takes those).
  */
 xeng_status xeng_correlate_delayed(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
                                    const int32_t* delays, int max_delay, int64_t t_prev,
                                    int accumulate, void* hip_stream);
+
+/*
+ * Delay compensation for any n and t (Sec. IV, as the paper lays it out: a
+ * kernel shifts each element's samples by its delay ahead of correlation).
+ * Arguments as for xeng_correlate_delayed, plus a caller workspace:
+ *   d_workspace  device memory of ws_bytes bytes, not overlapping d_in or d_vis.
+ * Where xeng_correlate_delayed applies (n <= 256, t % 64 == 0) the same fused
+ * kernels run and the workspace is not touched. Otherwise windows of frame
+ * samples are written delay-aligned into the workspace as dense
+ * uint8_t[f][window][n] frames (an HBM-bound copy) and correlated by the
+ * kernel xeng_correlate would use, each window after the first adding to the
+ * sums; the window is as long as ws_bytes allows (a multiple of 128 samples),
+ * so a workspace of xeng_delayed_workspace_bytes(n, f, t) runs in one pass.
+ * Results are the same integers as xeng_correlate_delayed gives. Errors as
+ * for xeng_correlate_delayed, and XENG_EINVAL for a workspace shorter than
+ * f * n * min(t, 128) bytes or one that overlaps d_in or d_vis.
+ */
+size_t xeng_delayed_workspace_bytes(int n, int f, int t);   /* 0: none needed */
+xeng_status xeng_correlate_delayed_ws(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
+                                      const int32_t* delays, int max_delay, int64_t t_prev,
+                                      int accumulate, void* d_workspace, size_t ws_bytes,
+                                      void* hip_stream);
 
 /*
  * The variant and time split xeng_correlate would use for a job of this shape

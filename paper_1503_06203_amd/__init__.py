@@ -122,10 +122,14 @@ def correlate_gated(x, vis, gate_of_block, block: int, t_prev=None, accumulate: 
     return vis
 
 
-def correlate_delayed(x, vis, delays, t_prev: int = 0, accumulate: bool = False, stream=None):
+def correlate_delayed(x, vis, delays, t_prev: int = 0, accumulate: bool = False, stream=None,
+                      workspace=None):
     """Delay compensation: x is uint8 [F][T + D][N] with D = max(delays) halo
     samples first; element e's frame sample s is x[:, D + s - delays[e], e].
-    vis int32 [F][N(N+1)/2][2] as for correlate()."""
+    vis int32 [F][N(N+1)/2][2] as for correlate(). Shapes the fused triangle
+    kernels take (N <= 256, T % 64 == 0) need no workspace; others shift the
+    samples into a workspace first (a uint8 GPU tensor; None allocates one
+    pass's worth)."""
     import ctypes
 
     import numpy as np
@@ -141,9 +145,23 @@ def correlate_delayed(x, vis, delays, t_prev: int = 0, accumulate: bool = False,
     if vis.dtype != torch.int32 or not vis.is_cuda or not vis.is_contiguous() or \
             vis.numel() != 2 * f * vis_entries(n):
         raise TypeError("vis must be a contiguous GPU int32 tensor [F][N(N+1)/2][2]")
-    check(lib().xeng_correlate_delayed(x.data_ptr(), vis.data_ptr(), n, f, t,
-                                       d.ctypes.data_as(ctypes.c_void_p), dmax, int(t_prev),
-                                       int(bool(accumulate)), _stream_ptr(stream)))
+    need = int(lib().xeng_delayed_workspace_bytes(n, f, t))
+    if need == 0 and workspace is None and n <= 256:
+        check(lib().xeng_correlate_delayed(x.data_ptr(), vis.data_ptr(), n, f, t,
+                                           d.ctypes.data_as(ctypes.c_void_p), dmax, int(t_prev),
+                                           int(bool(accumulate)), _stream_ptr(stream)))
+        return vis
+    if workspace is None and need > 0:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    if workspace is not None and (workspace.dtype != torch.uint8 or not workspace.is_cuda or
+                                  not workspace.is_contiguous()):
+        raise TypeError("workspace must be a contiguous GPU uint8 tensor")
+    ws_ptr = workspace.data_ptr() if workspace is not None and workspace.numel() else None
+    ws_len = workspace.numel() if workspace is not None else 0
+    check(lib().xeng_correlate_delayed_ws(x.data_ptr(), vis.data_ptr(), n, f, t,
+                                          d.ctypes.data_as(ctypes.c_void_p), dmax, int(t_prev),
+                                          int(bool(accumulate)), ws_ptr, ws_len,
+                                          _stream_ptr(stream)))
     return vis
 
 

@@ -42,6 +42,12 @@ hipError_t launch_rect(const uint8_t* in, int32_t* vis, int n, int f, int t, int
                        int64_t cs, int t0, int t_count, int accumulate, int split,
                        hipStream_t stream);
 int64_t rect_units_per_channel(int n);
+// launch_rect over several sample segments [seg_t0[k], seg_t_end[k]) of each
+// channel (host arrays, 1 <= count <= tri_max_segments()), summed into one
+// result; otherwise as launch_rect with t0 = 0, t_count = t.
+hipError_t launch_rect_segments(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                                int64_t cs, const int32_t* seg_t0, const int32_t* seg_t_end,
+                                int count, int accumulate, int split, hipStream_t stream);
 
 // Kernel for arrays of at most small_max_elements() elements (n % 4 == 0,
 // 4-byte aligned input), bound by the input stream: each wave correlates one
@@ -52,6 +58,20 @@ hipError_t launch_small(const uint8_t* in, int32_t* vis, int n, int f, int t, in
                         int64_t cs, int t0, int t_count, int accumulate, int cus,
                         hipStream_t stream);
 int small_max_elements();
+
+// Delay compensation ahead of correlation (any n): writes the delay-aligned
+// window of tc frame samples starting at frame sample t0 as a dense
+// uint8[f][tc][n] buffer,
+//   out[c][s][e] = in[c][max_delay + t0 + s - delays[e]][e],
+// for the elements [e_begin, e_begin + e_count) (e_count <= kShiftGroupElems;
+// their delays travel as kernel arguments). in is uint8[f][t_in][n] with
+// t_in >= max_delay + t0 + tc; delays is a host array of n values in
+// [0, max_delay]. Returns hipErrorInvalidValue for arguments out of range.
+constexpr int kShiftGroupElems = 1024;
+hipError_t launch_shift(const uint8_t* in, uint8_t* out, int n, int f, int t_in, int max_delay,
+                        int t0, int tc, int e_begin, int e_count, const int32_t* delays,
+                        hipStream_t stream);
+int shift_tile_rows();
 
 // Triangle kernel for n <= tri_max_elements() (n % 4 == 0, 4-byte aligned
 // input): one workgroup per channel (times split) computes the channel's whole

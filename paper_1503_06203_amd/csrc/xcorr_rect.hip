@@ -93,10 +93,18 @@ struct RectParams {
   int atomic_out;
 };
 
+using tri::kDense;
+using tri::kSegments;
+using tri::TriSegments;
+
 // Tile rows 128I .. 128I+127, columns 256J .. 256J+255, 128I < 256J.
+// kMode: kDense sums samples [t0, t_end); kSegments sums the sample segments
+// of *sg (the runs of one gate), stage by stage as the triangle kernel does.
+template <int kMode>
 __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, int col0, int sb,
                                          int se, uint8_t* craw0, uint8_t* craw1, uint8_t* rraw0,
-                                         uint8_t* rraw1, uint8_t* dec) {
+                                         uint8_t* rraw1, uint8_t* dec,
+                                         const TriSegments* sg = nullptr) {
   const int tid = tri::opaque_tid();
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int half = lane >> 5, l32 = lane & 31;
@@ -114,9 +122,24 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
   const uint32_t voff_r =
       (row0 + 4 * l32 < n) ? (uint32_t)(row0 + 4 * l32) + (uint32_t)(half * ss) : kOob;
   const int t_stop = min(p.t_end, p.t0 + se * kStage);   // samples [t0 + sb*64, t_stop)
+  // first sample of stage st and the end of its samples; in the segment mode
+  // stages past se (loaded ahead, never multiplied) are empty
+  auto stage_span = [&](int st, int& first_row, int& stop) {
+    if (kMode == kSegments) {
+      int k = 0;
+      while (k + 1 < sg->count && sg->stage0[k + 1] <= st) ++k;
+      first_row = sg->t0[k] + (st - sg->stage0[k]) * kStage;
+      stop = st < se ? sg->t_end[k] : first_row;
+    } else {
+      first_row = p.t0 + st * kStage;
+      stop = t_stop;
+    }
+  };
   auto fetch = [&](uint8_t* craw, uint8_t* rraw, int st) {
-    const int first = __builtin_amdgcn_readfirstlane(p.t0 + st * kStage + 8 * wave);
-    const int64_t bytes = t_stop > first ? (int64_t)(t_stop - first - 1) * ss + n : 0;
+    int row0_st, stop;
+    stage_span(st, row0_st, stop);
+    const int first = __builtin_amdgcn_readfirstlane(row0_st + 8 * wave);
+    const int64_t bytes = stop > first ? (int64_t)(stop - first - 1) * ss + n : 0;
     const int records = bytes <= 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : (int)bytes);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(chan + (int64_t)first * ss), 0, records, 0x00020000);
@@ -281,7 +304,18 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
   }
   lds_barrier();
   // samples this workgroup summed
-  const uint32_t re_const = 128u * (uint32_t)max(0, t_stop - (p.t0 + sb * kStage));
+  int t_sum = max(0, t_stop - (p.t0 + sb * kStage));
+  if (kMode == kSegments) {
+    // the samples of each segment that fall into stages [sb, se)
+    t_sum = 0;
+    for (int k = 0; k < sg->count; ++k) {
+      const int lo = max(sb, sg->stage0[k]), hi = min(se, sg->stage0[k + 1]);
+      if (lo < hi)
+        t_sum += min(sg->t_end[k], sg->t0[k] + (hi - sg->stage0[k]) * kStage) -
+                 (sg->t0[k] + (lo - sg->stage0[k]) * kStage);
+    }
+  }
+  const uint32_t re_const = 128u * (uint32_t)t_sum;
 
   // ---- epilogue: masked writes of i <= j < n into the packed triangle ------------
   const int64_t n64 = n;
@@ -333,9 +367,11 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
 // Piece u of a channel: u < nbc is diagonal square u; the others are tiles,
 // column block by column block (column block J >= 1 holds the 2J row blocks
 // above its square, J (J - 1) tiles come before it).
+template <int kMode = kDense>
 __device__ __forceinline__ void rect_piece(const RectParams& p, int ch, int u, int sb, int se,
                                            uint8_t* craw0, uint8_t* craw1, uint8_t* rraw0,
-                                           uint8_t* rraw1, uint8_t* dec) {
+                                           uint8_t* rraw1, uint8_t* dec,
+                                           const TriSegments* sg = nullptr) {
   if (u < p.nbc) {
     tri::TriParams tp;
     tp.in = p.in;
@@ -354,13 +390,17 @@ __device__ __forceinline__ void rect_piece(const RectParams& p, int ch, int u, i
     tp.total_stages = p.total_stages;
     tp.accumulate = p.accumulate;
     tp.atomic_out = p.atomic_out;
-    tri::tri_channel(tp, ch, sb, se, craw0, craw1, dec);
+    if (kMode == kSegments)
+      tri::tri_channel_t<kSegments>(tp, ch, sb, se, craw0, craw1, dec, nullptr, tri::GathSlots{},
+                                    sg);
+    else
+      tri::tri_channel(tp, ch, sb, se, craw0, craw1, dec);
   } else {
     const int r = u - p.nbc;
     int J = 1;
     while ((J + 1) * J <= r) ++J;
     const int I = r - J * (J - 1);
-    rect_run(p, ch, kRows * I, kCols * J, sb, se, craw0, craw1, rraw0, rraw1, dec);
+    rect_run<kMode>(p, ch, kRows * I, kCols * J, sb, se, craw0, craw1, rraw0, rraw1, dec, sg);
   }
 }
 
@@ -386,6 +426,28 @@ __global__ __launch_bounds__(kThreads, 1) void xcorr_rect_kernel(RectParams p) {
   const int se = min(sb + p.stages_per_split, p.total_stages);
   if (sb >= se) return;
   rect_piece(p, ch, u, sb, se, craw0, craw1, rraw0, rraw1, dec);
+}
+
+// The same pieces over several sample segments of each channel summed into
+// one result (the runs of one gate of a gated correlation): the stage loop
+// runs over the segments' stages.
+__global__ __launch_bounds__(kThreads, 1) void xcorr_rect_segments_kernel(RectParams p,
+                                                                          TriSegments sg) {
+  __shared__ __attribute__((aligned(16))) uint8_t craw0[kColRaw];
+  __shared__ __attribute__((aligned(16))) uint8_t craw1[kColRaw];
+  __shared__ __attribute__((aligned(16))) uint8_t rraw0[kRowRaw];
+  __shared__ __attribute__((aligned(16))) uint8_t rraw1[kRowRaw];
+  __shared__ __attribute__((aligned(16))) uint8_t dec[kDecBytes];
+  const int logical = xcd_logical_id(blockIdx.x, gridDim.x);
+  const int per_ch = p.units * p.split;
+  const int ch = __builtin_amdgcn_readfirstlane(logical / per_ch);
+  const int rest = logical - ch * per_ch;
+  const int u = __builtin_amdgcn_readfirstlane(rest / p.split);
+  const int part = rest - u * p.split;
+  const int sb = part * p.stages_per_split;
+  const int se = min(sb + p.stages_per_split, p.total_stages);
+  if (sb >= se) return;
+  rect_piece<kSegments>(p, ch, u, sb, se, craw0, craw1, rraw0, rraw1, dec, &sg);
 }
 
 // Persistent workgroups over a queue of pieces of many jobs (batched mode and
@@ -491,6 +553,49 @@ hipError_t launch_queue(void* d_ws, int64_t items, int grid, hipStream_t stream)
 int64_t rect_units_per_channel(int n) {
   const int64_t nbc = (n + kCols - 1) / kCols;
   return nbc * nbc;
+}
+
+hipError_t launch_rect_segments(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                                int64_t cs, const int32_t* seg_t0, const int32_t* seg_t_end,
+                                int count, int accumulate, int split, hipStream_t stream) {
+  if (n < 1 || n % 4 != 0) return hipErrorInvalidValue;
+  if (count < 1 || count > tri::kMaxSegments) return hipErrorInvalidValue;
+  TriSegments sg;
+  sg.count = count;
+  int stages = 0;
+  for (int k = 0; k < count; ++k) {
+    if (seg_t0[k] < 0 || seg_t_end[k] <= seg_t0[k] || seg_t_end[k] > t)
+      return hipErrorInvalidValue;
+    sg.t0[k] = seg_t0[k];
+    sg.t_end[k] = seg_t_end[k];
+    sg.stage0[k] = stages;
+    stages += (seg_t_end[k] - seg_t0[k] + kStage - 1) / kStage;
+  }
+  sg.stage0[count] = stages;
+  for (int k = count; k < tri::kMaxSegments; ++k) sg.t0[k] = sg.t_end[k] = 0;
+  RectParams p;
+  p.in = in;
+  p.vis = vis;
+  p.n = n;
+  p.f = f;
+  p.t = t;
+  p.ss = ss;
+  p.cs = cs;
+  p.t0 = 0;
+  p.t_end = t;
+  p.nbc = (n + kCols - 1) / kCols;
+  p.units = p.nbc * p.nbc;
+  p.total_stages = stages;
+  if (split < 1) split = 1;
+  if (split > stages) split = stages;
+  p.split = split;
+  p.stages_per_split = (stages + split - 1) / split;
+  p.accumulate = accumulate;
+  p.atomic_out = split > 1;
+  const int64_t grid = (int64_t)f * p.units * split;
+  if (f <= 0 || grid <= 0 || grid > 0x7fffffff) return hipErrorInvalidConfiguration;
+  xcorr_rect_segments_kernel<<<dim3((unsigned)grid), dim3(kThreads), 0, stream>>>(p, sg);
+  return hipGetLastError();
 }
 
 hipError_t launch_rect(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,

@@ -343,10 +343,12 @@ xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates,
   }
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   std::vector<int64_t> held(gates, 0);                           // samples summed in this call
-  if (n <= xeng::tri_max_elements() && t > 0) {
-    // Triangle kernel: all runs of one gate in one launch (up to
-    // tri_max_segments() runs each), so a gate's accumulators are read and
-    // written once per launch instead of once per run.
+  if (t > 0) {
+    // All runs of one gate in one launch (up to tri_max_segments() runs each):
+    // the triangle kernel for n <= 256, else the kernel of diagonal squares and
+    // tiles, so a gate's accumulators are read and written once per launch
+    // instead of once per run.
+    const bool tri = n <= xeng::tri_max_elements();
     std::vector<std::vector<int32_t>> run_t0(gates), run_t1(gates);
     for (int64_t k = 0; k < nblocks;) {
       const int g = gate_of_block[k];
@@ -366,33 +368,24 @@ xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates,
         int64_t samples = 0;
         for (int r = 0; r < cnt; ++r) samples += run_t1[g][c + r] - run_t0[g][c + r];
         const bool first = !accumulate && held[g] == 0;
-        const int split = xeng::tri_auto_split(f, samples, xeng::device_cu_count());
+        const int cus = xeng::device_cu_count();
+        const int split = tri ? xeng::tri_auto_split(f, samples, cus)
+                              : xeng::rect_auto_split(n, f, samples, cus);
         if (first && split > 1) {
           hipError_t e = xeng::launch_fill_zero(vis_g, set_pairs, stream);
           if (e != hipSuccess) return device_error(e, "zero fill");
         }
-        hipError_t e = xeng::launch_tri_segments(d_in, vis_g, n, f, t, n, (int64_t)t * n,
-                                                 run_t0[g].data() + c, run_t1[g].data() + c, cnt,
-                                                 first ? 0 : 1, split, stream);
+        hipError_t e =
+            tri ? xeng::launch_tri_segments(d_in, vis_g, n, f, t, n, (int64_t)t * n,
+                                            run_t0[g].data() + c, run_t1[g].data() + c, cnt,
+                                            first ? 0 : 1, split, stream)
+                : xeng::launch_rect_segments(d_in, vis_g, n, f, t, n, (int64_t)t * n,
+                                             run_t0[g].data() + c, run_t1[g].data() + c, cnt,
+                                             first ? 0 : 1, split, stream);
         if (e != hipSuccess) return device_error(e, "gated correlation launch");
         held[g] += samples;
       }
     }
-  }
-  for (int64_t k = 0; k < nblocks && n > xeng::tri_max_elements();) {
-    const int g = gate_of_block[k];
-    int64_t e = k + 1;
-    while (e < nblocks && gate_of_block[e] == g) ++e;
-    if (g != 0xFF) {
-      const int64_t s0 = k * (int64_t)block, s1 = std::min<int64_t>((int64_t)t, e * (int64_t)block);
-      const int first = !accumulate && held[g] == 0;
-      const int64_t prev = (accumulate ? t_prev[g] : 0) + held[g];
-      st = correlate_impl(d_in + s0 * n, d_vis + (int64_t)g * set_pairs * 2, n, f, (int)(s1 - s0),
-                          n, (int64_t)t * n, first ? 0 : prev, first ? 0 : 1, -1, 0, hip_stream);
-      if (st != XENG_OK) return st;
-      held[g] += s1 - s0;
-    }
-    k = e;
   }
   if (!accumulate) {
     // gates that received no samples are zero
@@ -405,37 +398,44 @@ xeng_status xeng_correlate_gated(const uint8_t* d_in, int32_t* d_vis, int gates,
   return XENG_OK;
 }
 
-xeng_status xeng_correlate_delayed(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
-                                   const int32_t* delays, int max_delay, int64_t t_prev,
-                                   int accumulate, void* hip_stream) {
-  if (n < 1 || n > xeng::tri_max_elements())
-    return fail(XENG_EINVAL, "delay compensation supports 1 <= n <= %d (got %d)",
-                xeng::tri_max_elements(), n);
+}  // extern "C"
+
+namespace {
+
+// Checks shared by both delay entry points: delays, the input extent
+// (t + max_delay samples per channel) and the int32 range.
+xeng_status check_delayed(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
+                          const int32_t* delays, int max_delay, int64_t t_prev, int accumulate,
+                          size_t* in_bytes, size_t* vis_bytes) {
+  if (n < 1) return fail(XENG_EINVAL, "need n >= 1 (got %d)", n);
   if (max_delay < 0 || max_delay > 65535)
     return fail(XENG_EINVAL, "max_delay must be in [0, 65535] (got %d)", max_delay);
-  if (t % xeng::tri_stage_samples() != 0)
-    return fail(XENG_EINVAL, "delay compensation needs t %% %d == 0 (got t=%d)",
-                xeng::tri_stage_samples(), t);
+  if (t < 0) return fail(XENG_EINVAL, "need t >= 0 (got %d)", t);
   if (delays == nullptr) return fail(XENG_EINVAL, "delays is NULL");
   for (int e = 0; e < n; ++e)
     if (delays[e] < 0 || delays[e] > max_delay)
       return fail(XENG_EINVAL, "delay of element %d is %d, outside [0, %d]", e, delays[e],
                   max_delay);
-  // the input holds t + max_delay samples per channel
-  size_t in_bytes = 0, vis_bytes = 0;
-  xeng_status st = check_job(d_in, d_vis, n, f, t + max_delay, t_prev, accumulate, &in_bytes,
-                             &vis_bytes);
+  if ((int64_t)t + max_delay > 0x7fffffff)
+    return fail(XENG_EINVAL, "t + max_delay exceeds 2^31 - 1 samples");
+  xeng_status st = check_job(d_in, d_vis, n, f, t + max_delay, t_prev, accumulate, in_bytes,
+                             vis_bytes);
   if (st != XENG_OK) return st;
   if (t_prev + (int64_t)t > XENG_MAX_SAMPLES)
     return fail(XENG_ERANGE, "t_prev + t = %lld exceeds %lld samples", (long long)(t_prev + t),
                 (long long)XENG_MAX_SAMPLES);
-  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-  const int64_t pairs = (int64_t)(vis_bytes / 8);
-  if (t == 0) {
-    if (accumulate) return XENG_OK;
-    hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
-    return e == hipSuccess ? XENG_OK : device_error(e, "zero fill");
-  }
+  return XENG_OK;
+}
+
+// The triangle kernel's fused forms: delays applied while staging (n <= 256,
+// t % 64 == 0, t > 0).
+bool delayed_fused_ok(int n, int t) {
+  return n <= xeng::tri_max_elements() && t > 0 && t % xeng::tri_stage_samples() == 0;
+}
+
+xeng_status delayed_fused(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
+                          const int32_t* delays, int max_delay, int accumulate, int64_t pairs,
+                          hipStream_t stream) {
   const int split = xeng::tri_auto_split(f, t, xeng::device_cu_count());
   if (split > 1 && !accumulate) {
     hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
@@ -444,6 +444,100 @@ xeng_status xeng_correlate_delayed(const uint8_t* d_in, int32_t* d_vis, int n, i
   hipError_t e = xeng::launch_tri_delayed(d_in, d_vis, n, f, t, delays, max_delay, accumulate,
                                           split, stream);
   return e == hipSuccess ? XENG_OK : device_error(e, "delay-compensated correlation launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+xeng_status xeng_correlate_delayed(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
+                                   const int32_t* delays, int max_delay, int64_t t_prev,
+                                   int accumulate, void* hip_stream) {
+  if (n < 1 || n > xeng::tri_max_elements())
+    return fail(XENG_EINVAL,
+                "delay compensation without a workspace supports 1 <= n <= %d (got %d); "
+                "xeng_correlate_delayed_ws takes any n",
+                xeng::tri_max_elements(), n);
+  if (t % xeng::tri_stage_samples() != 0)
+    return fail(XENG_EINVAL,
+                "delay compensation without a workspace needs t %% %d == 0 (got t=%d); "
+                "xeng_correlate_delayed_ws takes any t",
+                xeng::tri_stage_samples(), t);
+  size_t in_bytes = 0, vis_bytes = 0;
+  xeng_status st = check_delayed(d_in, d_vis, n, f, t, delays, max_delay, t_prev, accumulate,
+                                 &in_bytes, &vis_bytes);
+  if (st != XENG_OK) return st;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  const int64_t pairs = (int64_t)(vis_bytes / 8);
+  if (t == 0) {
+    if (accumulate) return XENG_OK;
+    hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
+    return e == hipSuccess ? XENG_OK : device_error(e, "zero fill");
+  }
+  return delayed_fused(d_in, d_vis, n, f, t, delays, max_delay, accumulate, pairs, stream);
+}
+
+size_t xeng_delayed_workspace_bytes(int n, int f, int t) {
+  if (n < 1 || f < 1 || t < 0) return 0;
+  if (t == 0 || delayed_fused_ok(n, t)) return 0;
+  return (size_t)f * (size_t)t * (size_t)n;
+}
+
+xeng_status xeng_correlate_delayed_ws(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t,
+                                      const int32_t* delays, int max_delay, int64_t t_prev,
+                                      int accumulate, void* d_workspace, size_t ws_bytes,
+                                      void* hip_stream) {
+  size_t in_bytes = 0, vis_bytes = 0;
+  xeng_status st = check_delayed(d_in, d_vis, n, f, t, delays, max_delay, t_prev, accumulate,
+                                 &in_bytes, &vis_bytes);
+  if (st != XENG_OK) return st;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  const int64_t pairs = (int64_t)(vis_bytes / 8);
+  if (t == 0) {
+    if (accumulate) return XENG_OK;
+    hipError_t e = xeng::launch_fill_zero(d_vis, pairs, stream);
+    return e == hipSuccess ? XENG_OK : device_error(e, "zero fill");
+  }
+  if (delayed_fused_ok(n, t))
+    return delayed_fused(d_in, d_vis, n, f, t, delays, max_delay, accumulate, pairs, stream);
+  // One delay common to all elements shifts every stream alike: the plain
+  // correlation of a sample window, read in place (dword-loadable input).
+  const bool common = std::all_of(delays, delays + n, [&](int32_t d) { return d == delays[0]; });
+  if (common && n % 4 == 0 && (uintptr_t)d_in % 4 == 0)
+    return correlate_impl(d_in + (int64_t)(max_delay - delays[0]) * n, d_vis, n, f, t, n,
+                          (int64_t)(t + max_delay) * n, t_prev, accumulate, -1, 0, hip_stream);
+  // Shift, then correlate: windows of `chunk` frame samples are written
+  // delay-aligned into the workspace and correlated like plain frames, each
+  // window after the first adding to the sums.
+  const int64_t row = (int64_t)f * n;                 // workspace bytes per frame sample
+  const int64_t min_rows = std::min<int64_t>(t, xeng::shift_tile_rows());
+  if (d_workspace == nullptr || (int64_t)ws_bytes < min_rows * row)
+    return fail(XENG_EINVAL,
+                "workspace of %zu bytes is too small: at least %lld bytes (%lld frame samples); "
+                "%zu bytes run in one pass",
+                ws_bytes, (long long)(min_rows * row), (long long)min_rows,
+                xeng_delayed_workspace_bytes(n, f, t));
+  int64_t chunk = std::min<int64_t>(t, (int64_t)ws_bytes / row);
+  if (chunk < t) chunk = chunk / xeng::shift_tile_rows() * xeng::shift_tile_rows();
+  uint8_t* buf = static_cast<uint8_t*>(d_workspace);
+  const size_t buf_bytes = (size_t)(chunk * row);
+  if (ranges_overlap(buf, buf_bytes, d_in, in_bytes) ||
+      ranges_overlap(buf, buf_bytes, d_vis, vis_bytes))
+    return fail(XENG_EINVAL, "the workspace overlaps d_in or d_vis");
+  for (int64_t t0 = 0; t0 < t; t0 += chunk) {
+    const int tc = (int)std::min<int64_t>(chunk, t - t0);
+    for (int e0 = 0; e0 < n; e0 += xeng::kShiftGroupElems) {
+      const int cnt = std::min(xeng::kShiftGroupElems, n - e0);
+      hipError_t e = xeng::launch_shift(d_in, buf, n, f, t + max_delay, max_delay, (int)t0, tc,
+                                        e0, cnt, delays, stream);
+      if (e != hipSuccess) return device_error(e, "delay shift launch");
+    }
+    const int acc = (accumulate || t0 > 0) ? 1 : 0;
+    const int64_t prev = acc ? (accumulate ? t_prev : 0) + t0 : 0;
+    st = correlate_impl(buf, d_vis, n, f, tc, n, (int64_t)tc * n, prev, acc, -1, 0, hip_stream);
+    if (st != XENG_OK) return st;
+  }
+  return XENG_OK;
 }
 
 xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* variant,

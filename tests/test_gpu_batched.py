@@ -145,8 +145,8 @@ def test_graph_captured_accumulating_then_overwriting():
     frame1 = [synth.quantized_gaussian(x.shape[0], x.shape[1], x.shape[2], 2.5, seed=70 + k,
                                        device=DEV) for k, (x, _) in enumerate(jobs)]
     plan.set_frame(frame1, accumulate=True)
-    if plan.split == 1:
-        pytest.skip("autotuner chose no time split on this device")
+    # (with no time split chosen there are no atomic adds, and the replays
+    # below still check that the graph follows the accumulate flags)
     plan.capture_graph()
     plan.replay()                              # frame 0 + frame 1
     torch.cuda.synchronize()

@@ -82,3 +82,32 @@ def test_gated_segments(f, t, n, block, gates):
         sched[3] = 1
     got = gated(x.to(DEV), sched, block, gates)
     assert_same(got, oracle.correlate_gated(x.numpy(), sched, block, gates), "gated segments")
+
+
+# Above 256 elements the runs of one gate go to the kernel of diagonal squares
+# and 128 x 256 tiles in one launch per gate (at most 32 runs per launch):
+# tails of both piece kinds (N = 260, 516), many short runs, runs off the
+# 64-sample stage grid, a long gate split along time, and the full-CHIME
+# array size.
+@pytest.mark.parametrize("f,t,n,block,gates", [(2, 4096, 260, 8, 2), (1, 16384, 512, 1024, 2),
+                                               (3, 2000, 516, 37, 3), (2, 8192, 2048, 1024, 2)])
+def test_gated_segments_large_n(f, t, n, block, gates):
+    print("gated segments f=%d t=%d n=%d block=%d gates=%d" % (f, t, n, block, gates), flush=True)
+    x = synth.quantized_gaussian(f, t, n, 2.5, seed=t + n + block + 5)
+    nb = (t + block - 1) // block
+    sched = (np.arange(nb) % gates).astype(np.uint8)
+    if block == 1024:
+        sched[:] = 0
+        sched[3] = 1
+        sched[-1] = 0xFF
+    got = gated(x.to(DEV), sched, block, gates)
+    assert_same(got, oracle.correlate_gated(x.numpy(), sched, block, gates), "gated segments")
+    if n == 2048:
+        # gates partition the samples: their sums add up to the plain correlation
+        import paper_1503_06203_amd as xe
+        keep = np.repeat(sched != 0xFF, block)[:t]
+        xs = x[:, torch.as_tensor(keep)].contiguous().to(DEV)
+        plain = xe.new_vis(n, f, device=DEV)
+        xe.correlate(xs, plain)
+        torch.cuda.synchronize()
+        assert torch.equal(got.sum(dim=0, dtype=torch.int64).to(torch.int32), plain)

@@ -62,7 +62,12 @@ def _plain(rng, seed):
 def _variant(rng, seed):
     import paper_1503_06203_amd as xe
     v = int(rng.integers(0, len(xe.variants())))
-    n = int(rng.integers(1, 257)) if v in (3, 4) else int(rng.integers(1, 600))
+    if v in (3, 4):                 # triangle kernels: n <= 256
+        n = int(rng.integers(1, 257))
+    elif v == 6:                    # small-array kernel: n <= 64
+        n = int(rng.integers(1, 65))
+    else:
+        n = int(rng.integers(1, 600))
     if v != 0:
         n = max(4, n - n % 4)
     f, t = int(rng.integers(1, 5)), int(rng.integers(1, 3000))

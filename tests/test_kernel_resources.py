@@ -59,7 +59,7 @@ def test_rect_kernel_has_no_scratch_and_fits_lds(tmp_path):
     # traffic into the vector-memory queue that the staging waits count on
     # (and its persistent queue form, which runs the same pieces per queue item)
     asm = device_asm("xcorr_rect.hip", tmp_path)
-    for kernel in ("xcorr_rect_kernel", "xcorr_queue_kernel"):
+    for kernel in ("xcorr_rect_kernel", "xcorr_rect_segments_kernel", "xcorr_queue_kernel"):
         assert kernel_field(asm, kernel, "amdhsa_private_segment_fixed_size") == 0, kernel
         assert kernel_field(asm, kernel, "amdhsa_group_segment_fixed_size") <= 160 * 1024, kernel
 
