@@ -26,8 +26,9 @@
  *   contributes at most 128 in magnitude; beyond that the call is refused.
  *
  * Memory and streams: every d_ pointer is device memory owned by the caller
- * (typically allocated through PyTorch). The library never allocates, frees or
- * keeps device memory. All GPU work is enqueued on the caller's hipStream_t
+ * (typically allocated through PyTorch). The library never allocates or frees
+ * device memory, and keeps none apart from one static array per device that
+ * only xeng_plan_run_static uses (XENG_STATIC_SCRATCH_BYTES). All GPU work is enqueued on the caller's hipStream_t
  * (passed as void*, NULL = the null stream) and returns without waiting;
  * buffers must stay valid until that work completes.
  *
@@ -46,6 +47,8 @@ extern "C" {
 #endif
 
 #define XENG_MAX_SAMPLES 16777215LL
+/* Size of the device array that xeng_plan_run_static uses on each GPU. */
+#define XENG_STATIC_SCRATCH_BYTES (8LL << 20)
 
 typedef enum xeng_status {
   XENG_OK = 0,
@@ -255,10 +258,27 @@ int64_t xeng_plan_items(const xeng_plan* plan);   /* pieces in the queue; -1 if 
 int xeng_plan_split(const xeng_plan* plan);       /* stages are split this many ways per tile */
 xeng_status xeng_plan_upload(xeng_plan* plan, void* d_workspace, void* hip_stream);
 /* Rebind every job to a new frame: d_in[k] (NULL keeps the inputs) and
- * accumulate (1: add to the sums, subject to the int32 range guard). */
+ * accumulate (1: add to the sums, subject to the int32 range guard). The job
+ * table is copied into d_workspace on hip_stream; with d_workspace NULL only
+ * the plan's host copy changes (for xeng_plan_run_static, which uploads the
+ * whole image on every call). */
 xeng_status xeng_plan_set_frame(xeng_plan* plan, const uint8_t* const* d_in, int accumulate,
                                 void* d_workspace, void* hip_stream);
 xeng_status xeng_plan_run(xeng_plan* plan, void* d_workspace, void* hip_stream);
+/* xeng_plan_run for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * plan's image lives in a static device array of XENG_STATIC_SCRATCH_BYTES
+ * that the library holds on each GPU it runs on until the process ends, so no
+ * workspace is passed and nothing is allocated. Each call copies the plan's
+ * whole image (its queue counters start at zero) into that array on
+ * hip_stream and then launches the same kernels as xeng_plan_run; results are
+ * bit-identical to it. No earlier xeng_plan_upload is needed; rebind frames
+ * with xeng_plan_set_frame(plan, d_in, accumulate, NULL, stream). Every call
+ * on one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (other streams, other threads) race and must be ordered by the caller.
+ * XENG_EINVAL for a NULL plan or a plan whose image exceeds the array (about
+ * 260 000 pieces); XENG_EDEVICE for a HIP error. */
+xeng_status xeng_plan_run_static(xeng_plan* plan, void* hip_stream);
 /* Capture one run into a HIP graph owned by the plan (uses a private stream),
  * and replay it on hip_stream. The graph reads the workspace captured with it. */
 xeng_status xeng_plan_graph_capture(xeng_plan* plan, void* d_workspace);

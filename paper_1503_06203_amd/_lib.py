@@ -72,6 +72,7 @@ SIGNATURES = {
     "xeng_plan_upload": (c_int, [c_vp, c_vp, c_vp]),
     "xeng_plan_set_frame": (c_int, [c_vp, ctypes.POINTER(c_vp), c_int, c_vp, c_vp]),
     "xeng_plan_run": (c_int, [c_vp, c_vp, c_vp]),
+    "xeng_plan_run_static": (c_int, [c_vp, c_vp]),
     "xeng_plan_graph_capture": (c_int, [c_vp, c_vp]),
     "xeng_plan_graph_launch": (c_int, [c_vp, c_vp]),
     "xeng_plan_autotune": (c_int, [c_vp, c_vp, c_vp, c_int, c_cp, c_f32p]),

@@ -25,9 +25,11 @@ class Plan:
 
     jobs: list of (x uint8[F][T][N], vis int32[F][N(N+1)/2][2]) or
     (x, vis, t_prev, accumulate) tuples, all on the same GPU.
+    workspace: False makes no device allocation at all; the plan then runs
+    only through run_static (the library's static device array).
     """
 
-    def __init__(self, jobs, tune_cache=None):
+    def __init__(self, jobs, tune_cache=None, workspace=True):
         import torch
         self._keep = []
         arr = (XengJob * len(jobs))()
@@ -44,9 +46,16 @@ class Plan:
         h = ctypes.c_void_p()
         check(lib().xeng_plan_create(ctypes.byref(h), arr, len(jobs), _cstr(tune_cache)))
         self._h = h
-        nbytes = int(lib().xeng_plan_workspace_bytes(h))
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=jobs[0][0].device)
-        check(lib().xeng_plan_upload(h, ctypes.c_void_p(self.workspace.data_ptr()), _stream()))
+        self.workspace = None
+        if workspace:
+            nbytes = int(lib().xeng_plan_workspace_bytes(h))
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=jobs[0][0].device)
+            check(lib().xeng_plan_upload(h, self._ws(), _stream()))
+
+    def _ws(self):
+        if self.workspace is None:
+            raise XengError(-1, "plan made without a workspace: use run_static()")
+        return ctypes.c_void_p(self.workspace.data_ptr())
 
     @property
     def items(self) -> int:
@@ -57,8 +66,12 @@ class Plan:
         return int(lib().xeng_plan_split(self._h))
 
     def run(self, stream=None):
-        check(lib().xeng_plan_run(self._h, ctypes.c_void_p(self.workspace.data_ptr()),
-                                  _stream(stream)))
+        check(lib().xeng_plan_run(self._h, self._ws(), _stream(stream)))
+
+    def run_static(self, stream=None):
+        """Run through the library's static device array (no workspace, no
+        allocation); calls that overlap on one GPU race."""
+        check(lib().xeng_plan_run_static(self._h, _stream(stream)))
 
     def set_frame(self, inputs=None, accumulate=True, stream=None):
         """Rebind every job to a new frame of inputs (same shapes)."""
@@ -68,21 +81,20 @@ class Plan:
                 raise ValueError("one input per job")
             ptrs = (ctypes.c_void_p * len(inputs))(*[x.data_ptr() for x in inputs])
             self._keep += list(inputs)
-        check(lib().xeng_plan_set_frame(self._h, ptrs, int(bool(accumulate)),
-                                        ctypes.c_void_p(self.workspace.data_ptr()),
+        ws = None if self.workspace is None else self._ws()
+        check(lib().xeng_plan_set_frame(self._h, ptrs, int(bool(accumulate)), ws,
                                         _stream(stream)))
 
     def capture_graph(self):
-        check(lib().xeng_plan_graph_capture(self._h, ctypes.c_void_p(self.workspace.data_ptr())))
+        check(lib().xeng_plan_graph_capture(self._h, self._ws()))
 
     def replay(self, stream=None):
         check(lib().xeng_plan_graph_launch(self._h, _stream(stream)))
 
     def autotune(self, reps: int = 3, tune_cache=None, stream=None) -> float:
         ms = ctypes.c_float(0.0)
-        check(lib().xeng_plan_autotune(self._h, ctypes.c_void_p(self.workspace.data_ptr()),
-                                       _stream(stream), int(reps), _cstr(tune_cache),
-                                       ctypes.byref(ms)))
+        check(lib().xeng_plan_autotune(self._h, self._ws(), _stream(stream), int(reps),
+                                       _cstr(tune_cache), ctypes.byref(ms)))
         return float(ms.value)
 
     def close(self):

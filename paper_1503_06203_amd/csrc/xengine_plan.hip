@@ -21,6 +21,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <sstream>
 #include <string>
@@ -245,7 +246,7 @@ xeng_status xeng_plan_upload(xeng_plan* plan, void* d_workspace, void* hip_strea
 xeng_status xeng_plan_set_frame(xeng_plan* plan, const uint8_t* const* d_in, int accumulate,
                                 void* d_workspace, void* hip_stream) {
   using namespace xeng;
-  if (plan == nullptr || d_workspace == nullptr) return fail(XENG_EINVAL, "null plan or workspace");
+  if (plan == nullptr) return fail(XENG_EINVAL, "null plan");
   if (accumulate != 0 && accumulate != 1) return fail(XENG_EINVAL, "accumulate must be 0 or 1");
   for (size_t k = 0; k < plan->jobs.size(); ++k) {
     if (d_in != nullptr && (d_in[k] == nullptr || (uintptr_t)d_in[k] % 4 != 0))
@@ -264,6 +265,7 @@ xeng_status xeng_plan_set_frame(xeng_plan* plan, const uint8_t* const* d_in, int
     if (d_in != nullptr) j.d_in = d_in[k];
   }
   write_jobs(plan);
+  if (d_workspace == nullptr) return XENG_OK;   // the plan's own copy only
   const size_t nj = queue_items_offset((int)plan->windows.size()) - queue_jobs_offset();
   hipError_t e = hipMemcpyAsync(static_cast<uint8_t*>(d_workspace) + queue_jobs_offset(),
                                 plan->image.data() + queue_jobs_offset(), nj,
@@ -380,3 +382,59 @@ void xeng_plan_destroy(xeng_plan* plan) {
 }
 
 }  // extern "C"
+
+// ---- plan runs that allocate nothing ---------------------------------------------
+// xeng_plan_run_static keeps the plan's device image (header, job table, piece
+// queue) in one file-scope device array instead of a caller workspace. In host
+// code the array's name is only a stand-in for the symbol; its device address
+// comes from hipGetSymbolAddress, once per device with that device current, and
+// only that address is ever handed to copies and kernels.
+namespace xeng {
+namespace {
+
+__device__ __align__(256) uint8_t scratch[XENG_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The current device's copy of scratch.
+xeng_status static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_error(e, "static scratch: current device");
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(XENG_EDEVICE, "static scratch: device %d beyond the %d supported", dev,
+                kMaxScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return device_error(e, "static scratch: symbol address");
+    if (ptr == nullptr) return fail(XENG_EDEVICE, "static scratch: no device address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return XENG_OK;
+}
+
+}  // namespace
+}  // namespace xeng
+
+extern "C" xeng_status xeng_plan_run_static(xeng_plan* plan, void* hip_stream) {
+  using namespace xeng;
+  if (plan == nullptr) return fail(XENG_EINVAL, "null plan");
+  if (plan->image.size() > (size_t)XENG_STATIC_SCRATCH_BYTES)
+    return fail(XENG_EINVAL,
+                "plan image of %zu bytes exceeds the static scratch of %lld bytes (%lld pieces "
+                "queued); use xeng_plan_run with a workspace",
+                plan->image.size(), (long long)XENG_STATIC_SCRATCH_BYTES, (long long)plan->items);
+  void* ws = nullptr;
+  xeng_status st = static_scratch(&ws);
+  if (st != XENG_OK) return st;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  // the whole image, header included: its queue cursors and counters start at
+  // zero whatever an earlier call left in the array
+  if ((st = upload(plan, ws, stream)) != XENG_OK) return st;
+  return launch(plan, ws, stream);
+}

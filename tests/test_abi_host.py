@@ -161,3 +161,23 @@ def test_plan_host_logic(lib):
     jobs[1] = XengJob(base_in, base_vis, 6, 1, 10, 0, 0)        # n % 4 != 0
     assert lib.xeng_plan_create(ctypes.byref(h), jobs, 3, None) == EINVAL
     assert b"n % 4" in lib.xeng_last_error()
+
+
+def test_static_plan_run_refuses_oversize_plan(lib):
+    """xeng_plan_run_static refuses, before any device work, a plan whose image
+    exceeds the static device array: 4097 channels x 64 pieces at N=2048 is
+    262 208 queue items of 32 bytes, more than XENG_STATIC_SCRATCH_BYTES."""
+    from paper_1503_06203_amd._lib import XengJob
+    import ctypes
+    text = open(HEADER).read()
+    limit = int(re.search(r"XENG_STATIC_SCRATCH_BYTES \((\d+)LL << (\d+)\)", text).group(1)) << 20
+    assert limit == 8 << 20
+    jobs = (XengJob * 1)()
+    jobs[0] = XengJob(0x100000000, 0x10000000000, 2048, 4097, 64, 0, 0)
+    h = ctypes.c_void_p()
+    assert lib.xeng_plan_create(ctypes.byref(h), jobs, 1, None) == 0
+    assert lib.xeng_plan_items(h) == 4097 * 64
+    assert lib.xeng_plan_run_static(h, None) == EINVAL
+    assert b"static scratch" in lib.xeng_last_error()
+    lib.xeng_plan_destroy(h)
+    assert lib.xeng_plan_run_static(None, None) == EINVAL
