@@ -56,11 +56,36 @@ def dispatched_kernel(n: int, f: int, t: int):
     return name, name, split
 
 
-def kernel_source_digest() -> str:
+# the source file of each kernel; its digest also covers the headers it includes
+KERNEL_SOURCE = {
+    "xcorr_rect_kernel": "xcorr_rect.hip",
+    "xcorr_tri_kernel": "xcorr_tri.hip",
+    "xcorr_small_kernel": "xcorr_small.hip",
+    "xcorr_tri_bf6_kernel": "xcorr_tri_bf6.hip",
+    "xcorr_wide8_kernel": "xcorr_wide.hip",
+    "xcorr_wide_kernel": "xcorr_wide.hip",
+    "xcorr_tile128_kernel": "xcorr_tile.hip",
+    "xcorr_shift_kernel": "xcorr_shift.hip",
+}
+
+
+def kernel_source_digest(kernel: str) -> str:
+    """Digest of the sources a kernel is compiled from (its file and the
+    package headers it includes, transitively): recorded HBM counters apply
+    only while it is unchanged."""
+    csrc = os.path.join(ROOT, "paper_1503_06203_amd", "csrc")
+    todo, seen = [KERNEL_SOURCE.get(kernel, "")], []
+    while todo:
+        name = todo.pop()
+        path = os.path.join(csrc, name)
+        if name in seen or not os.path.isfile(path):
+            continue
+        seen.append(name)
+        todo += re.findall(r'#include "([^"]+)"', open(path).read())
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1503_06203_amd", "csrc", "*"))):
-        with open(p, "rb") as fh:
-            h.update(fh.read())
+    for name in sorted(seen):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -243,18 +268,17 @@ def bench_delayed(w, steps: int, warmup: int):
     return out
 
 
-def bench_bf6(w, steps: int, warmup: int):
-    """The exact bf6 path (the triangle kernel on the f8f6f4 matrix cores,
-    variant 4) on the same workload, reported apart from the int8 metric: its
-    roofline is the fp6 peak. Also checks that its result equals the default
-    path's bit for bit."""
+def bench_bf6(w, steps: int, warmup: int, variant: int = 4):
+    """The exact bf6 path (the triangle kernel, variant 4, or the kernel of
+    squares and tiles, variant 7, on the f8f6f4 matrix cores) on the workload,
+    reported apart from the int8 metric: its roofline is the fp6 peak. Also
+    checks that its result equals the default path's bit for bit."""
     import torch
 
     import paper_1503_06203_amd as xe
     import synth
     from paper_1503_06203_amd import metrics
 
-    variant = 4
     x = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, w.seeds()[0], common=w.common,
                                  device="cuda:0")
     vis = xe.new_vis(w.n, w.f)
@@ -267,7 +291,8 @@ def bench_bf6(w, steps: int, warmup: int):
     del x, vis, ref
     torch.cuda.empty_cache()
     achieved = ops / kern_s / 1e12
-    return {"variant": xe.variants()[variant], "dtype": "bf6 (E3M2), fp32 accumulate",
+    return {"workload": w.name, "variant": xe.variants()[variant],
+            "dtype": "bf6 (E3M2), fp32 accumulate",
             "value": round(ops / (wall / steps) / 1e12, 3), "unit": "TOPS",
             "ms_per_step": round(wall / steps * 1e3, 5), "kernel_ms": round(kern_s * 1e3, 5),
             "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
@@ -277,9 +302,11 @@ def bench_bf6(w, steps: int, warmup: int):
 
 
 def cpu_baseline(w, budget_s: float = 15.0):
-    """Time the CPU oracle on a bounded sample of the workload: whole channels
-    (all N elements, all T samples) as many as fit about budget_s, estimated
-    from a one-channel calibration on a slice of the time axis."""
+    """Time the CPU oracle on a bounded sample of the workload: one channel
+    (all N elements) over a prefix of its samples, doubled from a short first
+    run until one run takes at least a sixth of budget_s or covers the whole
+    channel; then as many whole channels as fit half the budget. The last
+    timed run is the reported sample (its own rate, nothing extrapolated)."""
     import numpy as np
 
     import oracle
@@ -287,33 +314,39 @@ def cpu_baseline(w, budget_s: float = 15.0):
     from paper_1503_06203_amd import metrics
 
     oracle.build(force=False)
+    drawn = {}
 
-    def draw(k, t):
-        x = synth.quantized_gaussian(k, w.t, w.n, w.sigma, w.seeds()[0], common=w.common)
-        return np.ascontiguousarray(x.numpy()[:, :t, :])
+    def timed(k, t):
+        if drawn.get("k", 0) < k:      # the workload's first k channels, drawn on the host
+            drawn["x"] = synth.quantized_gaussian(k, w.t, w.n, w.sigma, w.seeds()[0],
+                                                  common=w.common).numpy()
+            drawn["k"] = k
+        sample = np.ascontiguousarray(drawn["x"][:k, :t, :])
+        t0 = time.perf_counter()
+        oracle.correlate(sample)
+        return time.perf_counter() - t0
 
-    t_cal = max(1, w.t // 32)
-    cal = draw(1, t_cal)
-    t0 = time.perf_counter()
-    oracle.correlate(cal)
-    per_sample = (time.perf_counter() - t0) / t_cal
-    t_use = w.t
-    if per_sample * w.t > 2 * budget_s:          # one whole channel is too long: fewer samples
-        t_use = max(t_cal, int(budget_s / per_sample))
-    k = int(max(1, min(w.f, budget_s / max(per_sample * t_use, 1e-6))))
-    sample = draw(k, t_use)
-    t0 = time.perf_counter()
-    oracle.correlate(sample)
-    dt = time.perf_counter() - t0
+    # the oracle's time per sample grows with the sample count (its working set
+    # leaves the caches), so the prefix at most doubles per run
+    k, t_use = 1, min(w.t, 1024)
+    dt = timed(k, t_use)
+    while dt < budget_s / 6 and t_use < w.t:
+        t_use = min(w.t, 2 * t_use)
+        dt = timed(k, t_use)
+    if t_use == w.t and dt < budget_s / 3 and w.f > 1:
+        k = int(max(1, min(w.f, 0.5 * budget_s / max(dt, 1e-3))))
+        if k > 1:
+            dt = timed(k, t_use)
     ops = metrics.effective_ops(w.n, k, t_use)
     return {"value": ops / dt / 1e12, "unit": "TOPS", "cores": oracle.threads(), "kind": "oracle",
-            "sample": "%d of %d channels, N=%d, T=%d of %d, first frame (%.3g effective ops "
-                      "in %.2f s)" % (k, w.f, w.n, t_use, w.t, ops, dt)}
+            "sample": "%d of %d channels, N=%d, first %d of %d samples, first frame "
+                      "(%.3g effective ops in %.2f s)" % (k, w.f, w.n, t_use, w.t, ops, dt)}
 
 
-def mfma_roofline(w, r, digest):
+def mfma_roofline(w, r):
     """Roofline object for an MFMA-bound workload measured by bench_workload."""
     kern, vname, vsplit = dispatched_kernel(w.n, w.f, w.t)
+    digest = kernel_source_digest(kern)
     return {
         "bound": "mfma",
         "achieved": round(r["kernel_tops"], 3),
@@ -331,7 +364,7 @@ def mfma_roofline(w, r, digest):
     }
 
 
-def bench_small_n(w, steps: int, warmup: int, digest: str):
+def bench_small_n(w, steps: int, warmup: int):
     """A small array (N=64): bound by HBM rather than the matrix cores. The
     roofline is the algorithmic bytes (input read once, output written once)
     per launch over the launch time, against 8 TB/s."""
@@ -339,6 +372,7 @@ def bench_small_n(w, steps: int, warmup: int, digest: str):
 
     r = bench_workload(w, steps, warmup)
     kern, vname, vsplit = dispatched_kernel(w.n, w.f, w.t)
+    digest = kernel_source_digest(kern)
     alg = metrics.algorithmic_bytes(w.n, w.f, w.t, accumulate=False)
     gbs = alg / (r["kernel_ms"] / 1e3) / 1e9
     return {"workload": w.name, "n": w.n, "f": w.f, "t": w.t,
@@ -351,6 +385,29 @@ def bench_small_n(w, steps: int, warmup: int, digest: str):
                          "kernel_ms": round(r["kernel_ms"], 5),
                          "algorithmic_bytes_per_launch": alg,
                          "mfma_frac": round(r["kernel_tops"] / PEAK_INT8_TOPS, 4)}}
+
+
+def bench_autotune(w, r):
+    """The autotuner on the workload's frame: the variant and split it keeps
+    and its time against the default choice's launch time from the headline
+    run. The choice is forgotten afterwards."""
+    import torch
+
+    import paper_1503_06203_amd as xe
+    import synth
+
+    x = synth.quantized_gaussian(w.f, w.t, w.n, w.sigma, w.seeds()[0], common=w.common,
+                                 device="cuda:0")
+    vis = xe.new_vis(w.n, w.f, device="cuda:0")
+    t0 = time.perf_counter()
+    v, split, ms = xe.autotune(x, vis, reps=2)
+    wall = time.perf_counter() - t0
+    xe.tune_clear()
+    del x, vis
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "variant": xe.variants()[v], "split": split,
+            "tuned_ms": round(ms, 5), "default_kernel_ms": round(r["kernel_ms"], 5),
+            "search_s": round(wall, 2)}
 
 
 def bench_latency(w, calls: int = 200):
@@ -538,7 +595,6 @@ def main():
         print(json.dumps(r), flush=True)
         return
 
-    digest = kernel_source_digest()
     w = workloads.WORKLOADS[args.workload]
     r = bench_workload(w, args.steps, args.warmup)
     if args.copy_reference:
@@ -567,25 +623,27 @@ def main():
                    "input": "uint8[F][T][N] 4+4-bit",
                    "output": "int32[F][N(N+1)/2][2]", "parallelism": "single-gpu"},
         "pct_int8_peak": round(100 * r["value"] / PEAK_INT8_TOPS, 2),
-        "roofline": mfma_roofline(w, r, digest),
+        "roofline": mfma_roofline(w, r),
     }
     if w.name == "small_n":
-        line["roofline"] = bench_small_n(w, args.steps, args.warmup, digest)["roofline"]
+        line["roofline"] = bench_small_n(w, args.steps, args.warmup)["roofline"]
     if not args.no_secondary and w.name == "large_n":
         pw = workloads.PATHFINDER
         pr = bench_workload(pw, 20, 3)
         line["pathfinder"] = {"workload": pw.name, "n": pw.n, "f": pw.f, "t": pw.t,
                               "value": round(pr["value"], 3), "unit": "TOPS",
                               "ms_per_step": round(pr["ms_per_step"], 5),
-                              "roofline": mfma_roofline(pw, pr, digest)}
+                              "roofline": mfma_roofline(pw, pr)}
         line["tiny"] = bench_latency(workloads.TINY)
-        line["small_n"] = bench_small_n(workloads.SMALL_N, 20, 3, digest)
+        line["small_n"] = bench_small_n(workloads.SMALL_N, 20, 3)
         line["time_major"] = bench_time_major(pw, 20, 3)
         line["gated"] = bench_gated(pw, 10, 2)
         line["delayed"] = bench_delayed(pw, 10, 2)
         line["large_n_gated"] = bench_gated(w, 5, 1)
         line["large_n_delayed"] = bench_delayed(w, 5, 1)
         line["bf6"] = bench_bf6(pw, 20, 3)
+        line["large_n_bf6"] = bench_bf6(w, 10, 2, variant=7)
+        line["autotune"] = bench_autotune(w, r)
         line["batched"] = bench_batched(10, 2)
         line["served"] = bench_served()
     if not args.no_cpu_baseline:

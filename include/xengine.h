@@ -113,6 +113,9 @@ xeng_status xeng_correlate(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
  *     ring in LDS; bound by HBM rather than the matrix cores at these sizes;
  *     the default for n <= 64. split_t is ignored (the kernel combines its
  *     time parts itself).
+ *   7 rect128x256_tri256_w8_bf6_mfma32x32x64  as 5 on the f8f6f4 matrix
+ *     cores with bf6 (E3M2) operands, exact as variant 4 is; split_t is
+ *     raised so that no workgroup sums more than 131 008 samples.
  */
 int xeng_variant_count(void);
 const char* xeng_variant_name(int variant);   /* NULL if out of range */
@@ -218,6 +221,32 @@ xeng_status xeng_correlate_delayed_ws(const uint8_t* d_in, int32_t* d_vis, int n
 xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* variant,
                                 int* split_t);
 
+/*
+ * Autotuner of plain calls. For one job class it times every kernel variant
+ * that can run the job (each with time splits 0 = its own choice, 1, 2, 4 and
+ * 8; reps timed runs after one untimed), keeps the fastest and records it in
+ * a process-wide table that xeng_correlate, xeng_correlate_strided and
+ * xeng_choose_variant consult for jobs of the same class where that variant
+ * can run them (otherwise the default rule applies). Every variant gives the
+ * same integers, so tuning changes speed only. A class is (device
+ * architecture, n, f, floor(log2 t)).
+ *   d_in, d_vis  a job as for xeng_correlate (overwritten: on success d_vis
+ *                holds the correlation of d_in)
+ *   tune_cache_path  may be NULL; otherwise one line per tuned class is
+ *                appended ("xeng-tune arch n f log2t variant split ms")
+ *   variant, split_t, best_ms  may be NULL; receive the choice
+ * XENG_EINVAL for an invalid job or t < 1, or an unwritable cache file.
+ * xeng_tune_load reads such a file (lines of other architectures and
+ * malformed lines are skipped, later lines replace earlier ones; entries may
+ * be NULL) and returns XENG_ENOTFOUND if it cannot be read; xeng_tune_clear
+ * forgets every choice.
+ */
+xeng_status xeng_autotune(const uint8_t* d_in, int32_t* d_vis, int n, int f, int t, int reps,
+                          const char* tune_cache_path, int* variant, int* split_t,
+                          float* best_ms, void* hip_stream);
+xeng_status xeng_tune_load(const char* tune_cache_path, int* entries);
+void xeng_tune_clear(void);
+
 /* ---- Batched mode: many jobs in one persistent launch ------------------------
  * A plan holds a list of independent correlation jobs (each as for
  * xeng_correlate) of mixed n, f and t and runs them all with one launch of a
@@ -299,9 +328,10 @@ void xeng_plan_destroy(xeng_plan* plan);
  * frames of one (n, f) shape) owns a device accumulator int32[f][n(n+1)/2][2]
  * that its frames add into; the job's first frame overwrites it. A call of
  * xeng_server_step() retires finished work and then launches, on each free
- * slot, one persistent-kernel step holding the oldest pending frame of every
- * job that has no frame in flight; frames that arrive meanwhile join later
- * steps, and up to max_inflight steps run concurrently on the device (each on
+ * slot, one persistent-kernel step holding the oldest pending frames of every
+ * job that has nothing in flight (up to 16 of a job whose accumulator already
+ * holds sums, added with int32 atomic adds; only its first frame, which
+ * overwrites, runs alone); frames that arrive meanwhile join later steps, and up to max_inflight steps run concurrently on the device (each on
  * a stream of its own, ordered after the work queued so far on hip_stream, the
  * stream the frames are produced on). Results are bit-identical to
  * xeng_correlate over each job's frames in order.

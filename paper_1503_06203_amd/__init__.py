@@ -14,8 +14,10 @@ from __future__ import annotations
 from . import metrics
 from ._lib import XengError, check, lib
 
-__all__ = ["correlate", "correlate_variant", "correlate_gated", "correlate_delayed", "choose_variant", "new_vis", "vis_entries", "tri_index",
-           "tile_count", "variants", "XengError", "metrics", "MAX_SAMPLES", "Plan", "Server"]
+__all__ = ["correlate", "correlate_variant", "correlate_gated", "correlate_delayed",
+           "choose_variant", "autotune", "tune_load", "tune_clear", "new_vis", "vis_entries",
+           "tri_index", "tile_count", "variants", "XengError", "metrics", "MAX_SAMPLES", "Plan",
+           "Server"]
 
 
 def __getattr__(name):
@@ -163,6 +165,36 @@ def correlate_delayed(x, vis, delays, t_prev: int = 0, accumulate: bool = False,
                                           int(bool(accumulate)), ws_ptr, ws_len,
                                           _stream_ptr(stream)))
     return vis
+
+
+def autotune(x, vis, reps: int = 3, tune_cache=None, stream=None):
+    """Time every kernel variant (and time split) that can correlate x into
+    vis, remember the fastest for this job class (device, N, F, log2 T) in the
+    library and optionally append it to the file tune_cache. vis receives the
+    correlation of x. Returns (variant id, split_t, milliseconds)."""
+    import ctypes
+    f, t, n = _check_tensors(x, vis)
+    if not x.is_contiguous():
+        raise TypeError("autotune needs a dense [F][T][N] input")
+    v, sp, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    check(lib().xeng_autotune(x.data_ptr(), vis.data_ptr(), n, f, t, int(reps),
+                              None if tune_cache is None else str(tune_cache).encode(),
+                              ctypes.byref(v), ctypes.byref(sp), ctypes.byref(ms),
+                              _stream_ptr(stream)))
+    return v.value, sp.value, ms.value
+
+
+def tune_load(tune_cache) -> int:
+    """Load tuned choices from a file written by autotune(); returns how many
+    apply to this device."""
+    import ctypes
+    k = ctypes.c_int()
+    check(lib().xeng_tune_load(str(tune_cache).encode(), ctypes.byref(k)))
+    return k.value
+
+
+def tune_clear() -> None:
+    lib().xeng_tune_clear()
 
 
 def choose_variant(n: int, f: int, t: int, aligned: bool = True):

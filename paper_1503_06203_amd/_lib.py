@@ -65,6 +65,10 @@ SIGNATURES = {
     "xeng_delayed_workspace_bytes": (c_size, [c_int, c_int, c_int]),
     "xeng_correlate_delayed_ws": (c_int, [c_vp, c_vp, c_int, c_int, c_int, c_vp, c_int, c_i64,
                                           c_int, c_vp, c_size, c_vp]),
+    "xeng_autotune": (c_int, [c_vp, c_vp, c_int, c_int, c_int, c_int, c_cp, c_intp, c_intp, c_f32p,
+                              c_vp]),
+    "xeng_tune_load": (c_int, [c_cp, c_intp]),
+    "xeng_tune_clear": (None, []),
     "xeng_plan_create": (c_int, [ctypes.POINTER(c_vp), ctypes.POINTER(XengJob), c_int, c_cp]),
     "xeng_plan_workspace_bytes": (c_size, [c_vp]),
     "xeng_plan_items": (c_i64, [c_vp]),

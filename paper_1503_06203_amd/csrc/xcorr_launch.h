@@ -42,6 +42,12 @@ hipError_t launch_rect(const uint8_t* in, int32_t* vis, int n, int f, int t, int
                        int64_t cs, int t0, int t_count, int accumulate, int split,
                        hipStream_t stream);
 int64_t rect_units_per_channel(int n);
+// launch_rect on bf6 operands (exact for 4-bit values): same arguments and
+// limits; split must keep every part within tri_bf6_min_split's bound
+// (returns hipErrorInvalidValue otherwise).
+hipError_t launch_rect_bf6(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
+                           int64_t cs, int t0, int t_count, int accumulate, int split,
+                           hipStream_t stream);
 // launch_rect over several sample segments [seg_t0[k], seg_t_end[k]) of each
 // channel (host arrays, 1 <= count <= tri_max_segments()), summed into one
 // result; otherwise as launch_rect with t0 = 0, t_count = t.

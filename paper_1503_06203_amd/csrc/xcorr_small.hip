@@ -13,10 +13,14 @@
 //
 // Every wave works alone on one channel over one part of its time axis, so the
 // stage loop has no barrier:
-//   * the wave's sample rows stream from HBM into a private ring of 16 steps
-//     of 16 samples in LDS (buffer_load ... lds, 64 bytes per sample row), 15
-//     steps ahead of use; the wave waits only for its own loads (they retire in
-//     issue order, so a count of outstanding loads names the step that is in).
+//   * the wave's sample rows stream from HBM into a ring of 8 steps of 16
+//     samples held in registers (4 dword loads per step, 64 bytes per sample
+//     row), 8 steps ahead of use; each step is written to the wave's own
+//     1 KiB slot in LDS just before it is read. The compiler tracks each
+//     register load exactly, so a step waits only for its own loads. (Loads
+//     straight into an LDS ring would make the compiler wait for every load
+//     in flight before a read wherever it cannot tell which ring slot a load
+//     writes, which is at least once per loop iteration.)
 //   * one ds_read_b64_tr_b8 per block and step hands each lane the 8 samples of
 //     one element that its MFMA operand needs: lanes 0-31 elements 32b .. 32b+31
 //     at samples 0-7 of the step, lanes 32-63 the same elements at samples 8-15.
@@ -31,6 +35,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "xcorr_device.h"
 #include "xcorr_launch.h"
@@ -41,7 +46,6 @@ namespace xeng {
 namespace {
 
 using tri::lds_v2i_ptr;
-using tri::lds_void_ptr;
 using tri::vm_wait;
 
 constexpr int kThreads = 512;                  // 8 waves
@@ -50,13 +54,20 @@ constexpr int kMaxElems = 64;
 constexpr int kStep = 16;                      // samples per MFMA step
 constexpr int kRow = 64;                       // LDS bytes per staged sample row
 constexpr int kStepBytes = kStep * kRow;       // 1 KiB
-constexpr int kRing = 16;                      // steps in a wave's ring
-constexpr int kAhead = kRing - 1;              // steps loaded ahead of the one in use
-constexpr int kLoadsPerStep = kStepBytes / 256;   // one load instruction fills 256 bytes
-constexpr int kWaveBytes = kRing * kStepBytes;    // 16 KiB
+constexpr int kAhead = 8;                      // steps loaded ahead of the one in use
+constexpr int kLoadsPerStep = kStepBytes / 256;   // one dword per lane fills 256 bytes
+constexpr int kWaveBytes = kStepBytes;         // the wave's LDS slot: one step
 constexpr uint32_t kOob = 0x80000000u;         // offset past every record: the load returns 0
 static_assert(kLoadsPerStep * kAhead <= 63, "outstanding loads fit the vmcnt field");
 static_assert(kWaves * kWaveBytes <= 160 * 1024, "LDS of one compute unit");
+
+// f(std::integral_constant<int, c>) for c = 0, 1, ...: one copy of the body
+// per value, so c is a constant in each (registers of the ring are then
+// addressed statically).
+template <class F, int... c>
+__device__ __forceinline__ void for_each_c(F&& f, std::integer_sequence<int, c...>) {
+  (f(std::integral_constant<int, c>{}), ...);
+}
 
 struct SmallParams {
   const uint8_t* in;
@@ -89,14 +100,16 @@ __device__ __forceinline__ void small_run(const SmallParams& p, uint8_t* ring_al
   const int total = p.t_end - p.t0;
   const int s0 = min(total, part * p.steps_per_part * kStep);
   const int s1 = min(total, s0 + p.steps_per_part * kStep);
-  const int nsteps = live ? (s1 - s0 + kStep - 1) / kStep : 0;
+  // whole laps of the register ring: steps past the part's end load past the
+  // record count, read 0x00 bytes and add nothing
+  const int nsteps = live ? ((s1 - s0 + kStep - 1) / kStep + kAhead - 1) / kAhead * kAhead : 0;
 
   // ---- loads: step k is rows [s0 + 16k, s0 + 16k + 16) of the part, four
   // instructions of four rows each (lane l: row l / 16, elements 4 (l % 16)).
   // Rows past s1 lie past the descriptor's record count and elements past n
   // use an offset past every record; both read 0x00, whose fields add nothing.
   const uint32_t voff = (4 * (lane & 15) < n) ? (uint32_t)((lane >> 4) * ss + 4 * (lane & 15)) : kOob;
-  auto fetch = [&](int k) {
+  auto fetch = [&](int k, uint32_t (&r)[kLoadsPerStep]) {
     const int first = p.t0 + s0 + k * kStep;     // uniform
     const int stop = p.t0 + s1;
     const int64_t bytes = stop > first ? (int64_t)(stop - first - 1) * ss + n : 0;
@@ -104,11 +117,17 @@ __device__ __forceinline__ void small_run(const SmallParams& p, uint8_t* ring_al
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(chan + (int64_t)(stop > first ? first : 0) * ss), 0, records,
         0x00020000);
-    uint8_t* const slot = ring + (k % kRing) * kStepBytes;
 #pragma unroll
     for (int q = 0; q < kLoadsPerStep; ++q)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_ptr)(slot + q * 256), 4,
-                                               voff + (uint32_t)(4 * q * ss), 0, 0, 0);
+      r[q] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, voff + (uint32_t)(4 * q * ss),
+                                                                 0, 0);
+  };
+  // a step's rows into the wave's LDS slot, in the layout the loads had
+  // (instruction q: rows 4q .. 4q+3, 64 bytes each)
+  auto put = [&](const uint32_t (&r)[kLoadsPerStep]) {
+#pragma unroll
+    for (int q = 0; q < kLoadsPerStep; ++q)
+      *reinterpret_cast<uint32_t*>(ring + q * 256 + 4 * lane) = r[q];
   };
 
   // ---- operands: lane (l32, half) reads 8 rows (samples 8 half ..) of its
@@ -116,9 +135,8 @@ __device__ __forceinline__ void small_run(const SmallParams& p, uint8_t* ring_al
   // first 8 elements and the odd lanes those of the next 8.
   const int lq = lane & 15, grp = lane >> 4;
   const int tr_off = (8 * (grp >> 1) + (lq >> 1)) * kRow + 16 * (grp & 1) + 8 * (lq & 1);
-  auto tr_read = [&](int k, int b) {
-    return __builtin_amdgcn_ds_read_tr8_b64_v2i32(
-        (lds_v2i_ptr)(ring + (k % kRing) * kStepBytes + tr_off + 32 * b));
+  auto tr_read = [&](int b) {
+    return __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i_ptr)(ring + tr_off + 32 * b));
   };
   uint32_t sum_re[kNB], sum_im[kNB];
   v16i acc_re[kPairs], acc_im[kPairs];
@@ -150,27 +168,34 @@ __device__ __forceinline__ void small_run(const SmallParams& p, uint8_t* ring_al
       }
   };
 
-  // ---- stream: every step issues the loads of step k + kAhead (past the
-  // part's end they read nothing, which keeps the count of loads per step
-  // fixed), waits until the loads of step k + 1 are in (at most the loads of
-  // steps k + 2 .. k + kAhead outstanding) and requests their transposing
-  // reads, then multiplies step k.
+  // ---- stream: step k's rows sit in regs[k % kAhead]. Every step issues the
+  // loads of step k + kAhead into the registers step k has vacated (past the
+  // part's end they read nothing), writes step k + 1 to the LDS slot (the
+  // compiler waits for exactly those loads) and requests its transposing
+  // reads, then multiplies step k. LDS operations of a wave run in order, so
+  // the next step's writes follow this step's reads of the slot.
   if (nsteps > 0) {
-#pragma unroll 1
-    for (int k = 0; k < kAhead; ++k) fetch(k);
-    vm_wait<kLoadsPerStep * (kAhead - 1)>();   // step 0 is in
+    uint32_t regs[kAhead][kLoadsPerStep];
     v2i cur[kNB], nxt[kNB];
+    for_each_c([&](auto cc) { fetch(decltype(cc)::value, regs[decltype(cc)::value]); },
+               std::make_integer_sequence<int, kAhead>{});
+    put(regs[0]);
 #pragma unroll
-    for (int b = 0; b < kNB; ++b) cur[b] = tr_read(0, b);
+    for (int b = 0; b < kNB; ++b) cur[b] = tr_read(b);
 #pragma unroll 1
-    for (int k = 0; k < nsteps; ++k) {
-      fetch(k + kAhead);
-      vm_wait<kLoadsPerStep * (kAhead - 1)>();   // step k + 1 is in
+    for (int k0 = 0; k0 < nsteps; k0 += kAhead) {
+      for_each_c(
+          [&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            fetch(k0 + c + kAhead, regs[c]);
+            put(regs[(c + 1) % kAhead]);
 #pragma unroll
-      for (int b = 0; b < kNB; ++b) nxt[b] = tr_read(k + 1, b);
-      step(cur);
+            for (int b = 0; b < kNB; ++b) nxt[b] = tr_read(b);
+            step(cur);
 #pragma unroll
-      for (int b = 0; b < kNB; ++b) cur[b] = nxt[b];
+            for (int b = 0; b < kNB; ++b) cur[b] = nxt[b];
+          },
+          std::make_integer_sequence<int, kAhead>{});
     }
     vm_wait<0>();
   }

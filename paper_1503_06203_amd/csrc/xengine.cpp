@@ -101,6 +101,7 @@ const Variant kVariants[] = {
     {"tri256_w8_bf6_mfma32x32x64"},       // as above, on bf6 operands (exact)
     {"rect128x256_tri256_w8_kc64_mfma32x32x32"},  // n % 4 == 0, 4-byte aligned input
     {"small64_w8_ring16_mfma32x32x32"},   // n <= 64, n % 4 == 0, 4-byte aligned input
+    {"rect128x256_tri256_w8_bf6_mfma32x32x64"},  // as 5, on bf6 operands (exact)
 };
 constexpr int kVariantTile128 = 0;
 constexpr int kVariantWide = 1;
@@ -109,6 +110,7 @@ constexpr int kVariantTri = 3;
 constexpr int kVariantTriBf6 = 4;
 constexpr int kVariantRect = 5;
 constexpr int kVariantSmall = 6;
+constexpr int kVariantRectBf6 = 7;
 constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // The kernel xeng_correlate uses: the triangle kernel where it applies (it
@@ -119,6 +121,21 @@ int default_variant(int n, bool aligned) {
   if (aligned && n <= xeng::small_max_elements()) return kVariantSmall;
   if (aligned && n <= xeng::tri_max_elements()) return kVariantTri;
   return aligned ? kVariantRect : kVariantTile128;
+}
+
+// Whether a variant can run a job (the rules correlate_impl enforces).
+bool variant_fits(int v, int n, bool aligned, bool dense) {
+  switch (v) {
+    case kVariantTile128: return dense;
+    case kVariantWide:
+    case kVariantWide8: return aligned && (int64_t)n * 32 < ((int64_t)1 << 31);
+    case kVariantRect:
+    case kVariantRectBf6: return aligned;
+    case kVariantTri:
+    case kVariantTriBf6: return aligned && n <= xeng::tri_max_elements();
+    case kVariantSmall: return aligned && n <= xeng::small_max_elements();
+    default: return false;
+  }
 }
 
 bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
@@ -223,6 +240,14 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
   }
   const bool aligned = (n % 4 == 0) && ((uintptr_t)d_in % 4 == 0);
   const bool tri_ok = aligned && n <= xeng::tri_max_elements();
+  if (variant == -1 && split_t == 0) {
+    // a choice the autotuner made for this job class, where it can run
+    int tv = -1, ts = 0;
+    if (xeng::tuned_choice(n, f, t, &tv, &ts) && variant_fits(tv, n, aligned, dense)) {
+      variant = tv;
+      split_t = ts;
+    }
+  }
   if (variant == -1) variant = default_variant(n, aligned);
   if (!dense && variant == kVariantTile128)
     return fail(XENG_EINVAL, "variant %s reads the dense [F][T][N] layout only",
@@ -233,7 +258,7 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
                 kVariants[variant].name);
   if (wide && (int64_t)n * 32 >= ((int64_t)1 << 31))
     return fail(XENG_EINVAL, "variant %s supports n < 2^26", kVariants[variant].name);
-  const bool rect = variant == kVariantRect;
+  const bool rect = variant == kVariantRect || variant == kVariantRectBf6;
   if (rect && !aligned)
     return fail(XENG_EINVAL, "variant %s needs n %% 4 == 0 and a 4-byte aligned input",
                 kVariants[variant].name);
@@ -247,11 +272,12 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
                 kVariants[variant].name, xeng::tri_max_elements());
   int split = split_t > 0 ? split_t : 1;
   if (tri && split_t == 0) split = xeng::tri_auto_split(f, t, xeng::device_cu_count());
-  // the bf6 kernel's fp32 sums are exact up to a bounded number of samples per part
-  if (variant == kVariantTriBf6) split = std::max(split, xeng::tri_bf6_min_split(t));
+  if (rect && split_t == 0) split = xeng::rect_auto_split(n, f, t, xeng::device_cu_count());
+  // the bf6 kernels' fp32 sums are exact up to a bounded number of samples per part
+  if (variant == kVariantTriBf6 || variant == kVariantRectBf6)
+    split = std::max(split, xeng::tri_bf6_min_split(t));
   if (variant == kVariantWide8 && split_t == 0)
     split = xeng::wide_auto_split(n, f, t, xeng::device_cu_count());
-  if (rect && split_t == 0) split = xeng::rect_auto_split(n, f, t, xeng::device_cu_count());
   // the small kernel combines its time parts itself: no split, no fill
   if (small) split = 1;
   if (split > 1 && !accumulate) {
@@ -264,6 +290,8 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
                            xeng::device_cu_count(), stream);
   } else if (variant == kVariantTri) {
     e = xeng::launch_tri(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
+  } else if (variant == kVariantRectBf6) {
+    e = xeng::launch_rect_bf6(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
   } else if (rect) {
     e = xeng::launch_rect(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
   } else if (variant == kVariantTriBf6) {
@@ -546,12 +574,25 @@ xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* var
     return fail(XENG_EINVAL, "need n >= 1, f >= 1, t >= 0 (got n=%d f=%d t=%d)", n, f, t);
   if (variant == nullptr || split_t == nullptr) return fail(XENG_EINVAL, "NULL output pointer");
   const bool aligned = input_aligned != 0 && n % 4 == 0;
-  const int v = default_variant(n, aligned);
+  // the autotuner's choice for this class where it can run, else the default
+  int v = default_variant(n, aligned), tv = -1, ts = 0;
+  if (xeng::tuned_choice(n, f, t, &tv, &ts) && variant_fits(tv, n, aligned, true))
+    v = tv;
+  else
+    ts = 0;
+  // the split correlate_impl then uses (ts = 0: the variant's own choice)
+  const int cus = xeng::device_cu_count();
+  int split = 1;
+  if (t > 0 && (v == kVariantTri || v == kVariantTriBf6)) split = xeng::tri_auto_split(f, t, cus);
+  if (t > 0 && v == kVariantWide8) split = xeng::wide_auto_split(n, f, t, cus);
+  if (t > 0 && (v == kVariantRect || v == kVariantRectBf6))
+    split = xeng::rect_auto_split(n, f, t, cus);
+  if (ts > 0) split = ts;
+  if ((v == kVariantTriBf6 || v == kVariantRectBf6) && t > 0)
+    split = std::max(split, xeng::tri_bf6_min_split(t));
+  if (v == kVariantSmall) split = 1;
   *variant = v;
-  *split_t = 1;
-  if (v == kVariantTri && t > 0) *split_t = xeng::tri_auto_split(f, t, xeng::device_cu_count());
-  if (v == kVariantWide8 && t > 0) *split_t = xeng::wide_auto_split(n, f, t, xeng::device_cu_count());
-  if (v == kVariantRect && t > 0) *split_t = xeng::rect_auto_split(n, f, t, xeng::device_cu_count());
+  *split_t = split;
   return XENG_OK;
 }
 

@@ -30,5 +30,8 @@ int auto_split(int64_t units, int64_t stages, int cus);
 int tri_auto_split(int f, int64_t t_count, int cus);
 int wide_auto_split(int n, int f, int64_t t_count, int cus);
 int rect_auto_split(int n, int f, int64_t t_count, int cus);
+// The autotuner's choice for this job class on the current device, if any
+// (variant id, split_t as xeng_correlate_variant takes it: 0 = the variant's own).
+bool tuned_choice(int n, int f, int t, int* variant, int* split);
 
 }  // namespace xeng

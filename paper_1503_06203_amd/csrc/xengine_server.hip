@@ -5,12 +5,14 @@
 // Each open job owns a device-resident int32 accumulator that frames add into
 // (paper Sec. III-A: new sums are added to the results already held). Frames
 // wait in a FIFO per job. A scheduling step first retires finished work, then,
-// while a workspace slot is free, takes the oldest pending frame of every job
-// that has no frame in flight, merges all their tiles into one queue image in
-// that slot and launches the persistent queue kernel on the slot's stream.
-// Frames that arrive while earlier steps run join the next step, and steps on
-// different slots overlap on the device; one job never has two frames in
-// flight, so its accumulator is only ever updated by one launch at a time.
+// while a workspace slot is free, takes the oldest pending frames of every job
+// that has nothing in flight (several of a job whose accumulator already holds
+// sums, combined with int32 atomic adds), merges all their pieces into one
+// queue image in that slot and launches the persistent queue kernel on the
+// slot's stream. Frames that arrive while earlier steps run join the next
+// step, and steps on different slots overlap on the device; a job is in at
+// most one step at a time, so its accumulator is only ever updated by one
+// launch at a time.
 // Admission is by memory: a job's accumulator must fit the HBM budget when it
 // is opened, and a frame is launched only while the bytes of frames in flight
 // plus all accumulators stay within the budget.
@@ -32,6 +34,9 @@
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// Frames of one job that one step may hold.
+constexpr size_t kMaxFramesPerJob = 16;
 
 struct Frame {
   uint64_t ticket;
@@ -127,11 +132,16 @@ xeng_status retire(xeng_server* s) {
 }
 
 // Build the queue image for the chosen frames into slot.image; returns false
-// if it would not fit the slot (or the host allocation failed).
+// if it would not fit the slot (or the host allocation failed). A job with
+// several frames in the step adds each of them into its sums with int32
+// atomic adds (any order gives the same integers); a job with one frame
+// stores or adds it directly.
 bool build_image(xeng_server* s, Slot& sl, const std::vector<std::pair<int64_t, Frame>>& picks) {
   using namespace xeng;
   const int stage = queue_stage_samples();
   const int nw = (int)picks.size();
+  std::map<int64_t, int> frames_of;
+  for (const auto& pk : picks) ++frames_of[pk.first];
   std::vector<QueueJob> table(nw);
   for (int w = 0; w < nw; ++w) {
     const ServerJob& J = s->jobs[picks[w].first];
@@ -150,7 +160,7 @@ bool build_image(xeng_server* s, Slot& sl, const std::vector<std::pair<int64_t, 
     q.units = q.nbc * q.nbc;
     q.total_stages = (fr.t + stage - 1) / stage;
     q.accumulate = J.summed ? 1 : 0;
-    q.atomic_out = 0;
+    q.atomic_out = frames_of[picks[w].first] > 1 ? 1 : 0;   // only for jobs already summed
     q.zero_first = 0;
   }
   uint8_t* image = nullptr;
@@ -257,25 +267,39 @@ xeng_status xeng_server_step(xeng_server* s, int* launched) {
   if (st != XENG_OK) return st;
   for (auto& sl : s->slots) {
     if (sl.busy) continue;
-    // oldest pending frame of every idle job, oldest first, within the budget
+    // The pending frames of every idle job, oldest first, within the budget:
+    // up to kMaxFramesPerJob of a job whose accumulator already holds sums
+    // (they add with atomics), one for a job whose first frame overwrites.
+    // A job's frames stay in order: a later frame is only taken after every
+    // earlier one of the same job.
     std::vector<std::pair<int64_t, Frame>> picks;
-    for (auto& kv : s->jobs)
-      if (!kv.second.busy && !kv.second.pending.empty())
-        picks.emplace_back(kv.first, kv.second.pending.front());
+    for (auto& kv : s->jobs) {
+      const ServerJob& J = kv.second;
+      if (J.busy) continue;
+      const size_t take = J.summed ? std::min(J.pending.size(), kMaxFramesPerJob)
+                                   : std::min<size_t>(J.pending.size(), 1);
+      for (size_t k = 0; k < take; ++k) picks.emplace_back(kv.first, J.pending[k]);
+    }
     if (picks.empty()) break;
-    std::sort(picks.begin(), picks.end(), [](const auto& a, const auto& b) {
+    std::stable_sort(picks.begin(), picks.end(), [](const auto& a, const auto& b) {
       return a.second.submit_us < b.second.submit_us;
     });
     std::vector<std::pair<int64_t, Frame>> chosen;
+    std::map<int64_t, size_t> skipped;
     size_t bytes = 0;
     for (const auto& pk : picks) {
       const ServerJob& J = s->jobs[pk.first];
       const size_t fb = (size_t)J.f * pk.second.t * J.n;
-      if (s->acc_total + s->inflight_bytes + bytes + fb > s->budget) continue;
+      if (skipped.count(pk.first) ||
+          s->acc_total + s->inflight_bytes + bytes + fb > s->budget) {
+        ++skipped[pk.first];     // this job's later frames wait as well
+        continue;
+      }
       chosen.push_back(pk);
       bytes += fb;
     }
     if (chosen.empty()) break;   // admission: wait for memory to free up
+    // drop newest frames until the image fits the slot
     while (!chosen.empty() && !build_image(s, sl, chosen)) chosen.pop_back();
     if (chosen.empty()) return fail(XENG_ENOMEM, "workspace slot too small for one frame");
     // the frames were produced on the caller's stream: order after that work
@@ -292,7 +316,7 @@ xeng_status xeng_server_step(xeng_server* s, int* launched) {
     sl.frame_bytes = 0;
     for (const auto& pk : chosen) {
       ServerJob& J = s->jobs[pk.first];
-      J.pending.pop_front();
+      J.pending.pop_front();     // chosen frames are each job's oldest, in order
       J.busy = true;
       J.summed = true;
       sl.tickets.push_back(pk.second.ticket);

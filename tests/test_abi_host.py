@@ -181,3 +181,36 @@ def test_static_plan_run_refuses_oversize_plan(lib):
     assert b"static scratch" in lib.xeng_last_error()
     lib.xeng_plan_destroy(h)
     assert lib.xeng_plan_run_static(None, None) == EINVAL
+
+
+def test_tune_table_host(lib, tmp_path):
+    """The autotuner's table and cache file on the host: without a device the
+    architecture reads "none", so lines for "none" apply and others do not;
+    a tuned (variant, split) replaces the default choice for its class
+    (n, f, floor(log2 t)) only, where the variant can run the job."""
+    import paper_1503_06203_amd as xe
+    xe.tune_clear()
+    default = xe.choose_variant(300, 2, 3000)
+    assert default[2].startswith("rect128x256")
+    default_t5000 = xe.choose_variant(300, 2, 5000)
+    default_f3 = xe.choose_variant(300, 3, 3000)
+    cache = tmp_path / "tune.txt"
+    cache.write_text("xeng-tune none 300 2 11 2 4 1.5\n"      # wide8, split 4, t in [2048, 4096)
+                     "xeng-tune gfx000 300 2 11 0 1 1.0\n"    # another device: skipped
+                     "garbage line\n"
+                     "xeng-tune none 300 2 11 1 2 1.2\n"      # a later line replaces the first
+                     "xeng-tune none 64 1 8 3 0 0.1\n")       # tri256 with its own split
+    assert xe.tune_load(cache) == 3
+    v, split, name = xe.choose_variant(300, 2, 3000)
+    assert (v, split) == (1, 2) and name.startswith("wide128x256_w4")
+    assert xe.choose_variant(300, 2, 5000) == default_t5000            # other t bucket
+    assert xe.choose_variant(300, 3, 3000) == default_f3               # other f
+    # a tuned variant that cannot run the call (unaligned input) is not used
+    assert xe.choose_variant(300, 2, 3000, aligned=False)[2].startswith("tile128")
+    assert xe.choose_variant(64, 1, 300)[2].startswith("tri256")
+    xe.tune_clear()
+    assert xe.choose_variant(300, 2, 3000)[:2] == default[:2]
+    assert xe.choose_variant(64, 1, 300)[2].startswith("small64")
+    with pytest.raises(xe.XengError) as e:
+        xe.tune_load(tmp_path / "missing.txt")
+    assert e.value.status == ENOTFOUND

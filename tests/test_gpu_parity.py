@@ -150,9 +150,11 @@ TRI_BF6_VARIANT = 4
 TRI_VARIANTS = [TRI_VARIANT, TRI_BF6_VARIANT]
 RECT_VARIANT = 5
 SMALL_VARIANT = 6
+RECT_BF6_VARIANT = 7
+RECT_VARIANTS = [RECT_VARIANT, RECT_BF6_VARIANT]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("f,t,n", VARIANT_SHAPES)
 def test_each_variant_matches_oracle(variant, f, t, n):
     x = synth.quantized_gaussian(f, t, n, 3.0, seed=f * 7919 + t * 31 + n)
@@ -273,37 +275,62 @@ def test_int32_boundary_on_gpu():
 # 128-row and 256-column edges, with partial last squares and tiles.
 @pytest.mark.parametrize("n", [260, 264, 380, 384, 388, 508, 512, 516, 636, 640, 768, 772, 1020,
                                1024, 1028])
-def test_rect_element_counts(n):
+@pytest.mark.parametrize("rv", RECT_VARIANTS)
+def test_rect_element_counts(n, rv):
     x = synth.quantized_gaussian(2, 301, n, 3.0, seed=3000 + n)
-    full_check(x, variant=RECT_VARIANT, split=1)
+    full_check(x, variant=rv, split=1)
 
 
 @pytest.mark.parametrize("t", [1, 7, 63, 64, 65, 127, 128, 129, 191, 192, 193, 257, 1000])
-def test_rect_sample_counts(t):
+@pytest.mark.parametrize("rv", RECT_VARIANTS)
+def test_rect_sample_counts(t, rv):
     x = synth.quantized_gaussian(1, t, 512, 2.5, seed=4000 + t)
-    full_check(x, variant=RECT_VARIANT, split=1)
+    full_check(x, variant=rv, split=1)
 
 
 @pytest.mark.parametrize("split", [2, 3, 5, 16])
 @pytest.mark.parametrize("t", [200, 1000, 4097])
-def test_rect_time_split(split, t):
+@pytest.mark.parametrize("rv", RECT_VARIANTS)
+def test_rect_time_split(split, t, rv):
     x = synth.quantized_gaussian(2, t, 516, 2.5, seed=split * 37 + t)
     xd = x.to(DEV)
     ref = gpu_correlate(xd, variant=0, split=1)
-    got = gpu_correlate(xd, variant=RECT_VARIANT, split=split)
+    got = gpu_correlate(xd, variant=rv, split=split)
     assert torch.equal(ref, got)
     assert_same(got, oracle.correlate(x.numpy()))
     prev = torch.randint(-1000, 1000, ref.shape, dtype=torch.int32, device=DEV)
-    got2 = gpu_correlate(xd, variant=RECT_VARIANT, split=split, prev=prev.clone(), t_prev=10)
+    got2 = gpu_correlate(xd, variant=rv, split=split, prev=prev.clone(), t_prev=10)
     assert torch.equal(got2, ref + prev)
 
 
-def test_rect_accumulate_and_many_channels():
+@pytest.mark.parametrize("rv", RECT_VARIANTS)
+def test_rect_accumulate_and_many_channels(rv):
     x = synth.quantized_gaussian(40, 130, 300, 2.5, seed=71)
     xd = x.to(DEV)
-    first = gpu_correlate(xd[:, :70].contiguous(), variant=RECT_VARIANT)
-    both = gpu_correlate(xd[:, 70:].contiguous(), variant=RECT_VARIANT, prev=first, t_prev=70)
+    first = gpu_correlate(xd[:, :70].contiguous(), variant=rv)
+    both = gpu_correlate(xd[:, 70:].contiguous(), variant=rv, prev=first, t_prev=70)
     assert_same(both, oracle.correlate(x.numpy()))
+
+
+@pytest.mark.parametrize("t", [131008, 131072, 262208])
+def test_rect_bf6_fp32_range(t):
+    # 0x00 bytes decode to (-8, -8): every sample adds 128 to Re of every pair.
+    # One workgroup may sum at most 131 008 samples in fp32 (2047 stages);
+    # beyond, the library raises the time split. Squares and tiles alike.
+    x = synth.constant_bytes(1, t, 520, 0x00, device=DEV)
+    vis = gpu_correlate(x, variant=RECT_BF6_VARIANT, split=1).cpu().numpy()
+    assert (vis[..., 0] == 128 * t).all() and (vis[..., 1] == 0).all()
+
+
+def test_rect_bf6_equals_int8_on_large_n_frame():
+    # the full-CHIME array size: bf6 and int8 give the same integers, and one
+    # whole channel matches the oracle
+    x = synth.quantized_gaussian(2, 8192, 2048, 3.0, seed=77)
+    xd = x.to(DEV)
+    a = gpu_correlate(xd, variant=RECT_BF6_VARIANT)
+    b = gpu_correlate(xd, variant=RECT_VARIANT)
+    assert torch.equal(a, b)
+    assert_same(a[:1], oracle.correlate(x[:1].numpy()), "bf6 channel 0")
 
 
 def test_rect_offset_sums_wrap_exactly():

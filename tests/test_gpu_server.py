@@ -154,3 +154,33 @@ def test_range_guard_and_bad_frames():
     with pytest.raises(xe.XengError):
         srv.submit(j + 99, torch.zeros((1, 4, n), dtype=torch.uint8, device=DEV))   # unknown job
     srv.close()
+
+
+def test_many_frames_of_a_job_in_one_step():
+    # Every frame is submitted before the first step: after a job's first frame
+    # (which overwrites its accumulator, alone in its step) a step takes up to
+    # 16 of its pending frames at once, each added into the sums with int32
+    # atomic adds. The sums must equal the frames run alone, in order, and the
+    # oracle; the budget admits only some of the frames at a time, so later
+    # frames of a job wait behind earlier ones.
+    shapes = {"a": (260, 2, 300), "b": (64, 3, 129), "c": (512, 1, 1000)}
+    nframes = {"a": 21, "b": 9, "c": 5}
+    frames = {k: [synth.quantized_gaussian(f, t, n, 2.5, seed=900 + 50 * i + j, device=DEV)
+                  for j in range(nframes[k])]
+              for i, (k, (n, f, t)) in enumerate(shapes.items())}
+    acc_bytes = sum(f * (n * (n + 1) // 2) * 8 for n, f, _ in shapes.values())
+    frame_bytes = max(n * f * t for n, f, t in shapes.values())
+    srv = xe.Server(hbm_budget=acc_bytes + 6 * frame_bytes, max_inflight=2)
+    acc = {k: xe.new_vis(n, f, device=DEV) for k, (n, f, t) in shapes.items()}
+    for v in acc.values():
+        v.fill_(-77)                       # the first frame of each job overwrites
+    ids = {k: srv.open_job(shapes[k][0], shapes[k][1], acc[k]) for k in shapes}
+    tickets = [srv.submit(ids[k], x) for k in shapes for x in frames[k]]
+    srv.drain()
+    for tk in tickets:
+        assert srv.poll(tk)[0]
+    for k in shapes:
+        assert torch.equal(acc[k], alone(frames[k])), k
+        x = torch.cat(frames[k], dim=1).cpu().numpy()
+        assert np.array_equal(acc[k].cpu().numpy().astype(np.int64), oracle.correlate(x)), k
+    srv.close()

@@ -64,6 +64,14 @@ def test_rect_kernel_has_no_scratch_and_fits_lds(tmp_path):
         assert kernel_field(asm, kernel, "amdhsa_group_segment_fixed_size") <= 160 * 1024, kernel
 
 
+def test_rect_bf6_kernel_has_no_scratch_and_fits_lds(tmp_path):
+    # 128 fp32 accumulators and bf6 operands (8-register tuples) per wave: the
+    # decode and the MFMA segments are kept apart so that they fit
+    asm = device_asm("xcorr_rect_bf6.hip", tmp_path)
+    assert kernel_field(asm, "xcorr_rect_bf6_kernel", "amdhsa_private_segment_fixed_size") == 0
+    assert kernel_field(asm, "xcorr_rect_bf6_kernel", "amdhsa_group_segment_fixed_size") <= 160 * 1024
+
+
 def test_small_kernel_has_no_scratch_and_fits_lds(tmp_path):
     # each wave waits on a count of its own outstanding loads; scratch
     # traffic would join that queue
