@@ -12,16 +12,19 @@
 // correlation's matrix-core time.
 //
 // One workgroup covers 256 elements of one channel over a strip of 2048
-// output rows. When the delays of its elements differ by at most kMaxSpread,
-// it slides down the strip through a ring of input rows in LDS: each input
-// row its output needs is loaded once, whole and coalesced (LDS-DMA, one
-// dword of 4 elements per lane, no registers), one chunk of 128 rows ahead of
-// use (by four loader waves), and each lane of the four gather waves collects
-// its 4 elements' bytes of a chunk from the rows their delays name and writes
-// them as one dword. Otherwise (a wider spread,
-// or an input that dword loads cannot read) every byte is read from HBM.
+// output rows. When the delays of its elements differ by at most kMaxSpread
+// (and every row of the block starts on a 16-byte boundary), it slides down
+// the strip through a ring of five LDS arrays of 128 input rows: each input
+// row its output needs is loaded once, whole and coalesced (16-byte LDS-DMA,
+// four rows per instruction), three chunks ahead of use by four loader
+// waves; each lane of the four gather waves collects its 4 elements' bytes of
+// a chunk from the rows their delays name and writes them as one dword.
+// Otherwise (a wider spread, or rows that such loads cannot read) every byte
+// is read from HBM.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <utility>
 
 #include "xcorr_launch.h"
 
@@ -35,15 +38,39 @@ constexpr int kBlockElems = 256;                // elements per workgroup, 4 per
 constexpr int kStripRows = 2048;                // output rows per workgroup
 constexpr int kChunk = 128;                     // output rows gathered per ring step
 constexpr int kMaxSpread = 128;                 // ring form: largest delay spread
-// The ring: three arrays of kChunk input rows. A chunk of output rows reads
-// two of them (its rows and up to kMaxSpread more), the third is loaded
-// meanwhile.
-constexpr int kRowStride = kBlockElems + 4;     // 65 dwords: rows start on different banks
+// The ring: kArrays arrays of kChunk input rows of 256 bytes. A chunk of
+// output rows reads two of them (its rows and up to kMaxSpread more) while the
+// next three are loaded. With 256-byte rows every lane reads only its own
+// dword column of any row, so the gathers meet no bank conflicts.
+constexpr int kArrays = 5;
+constexpr int kRowBytes = kBlockElems;
+constexpr int kArrayBytes = kChunk * kRowBytes;   // 32 KiB
+constexpr int kRowsPerLoad = 1024 / kRowBytes;    // a 16-byte LDS-DMA load fills 1 KiB
+constexpr int kLoaders = kWaves / 2;
+constexpr int kLoadsPerChunk = kChunk / kRowsPerLoad / kLoaders;   // per loader wave
 constexpr uint32_t kOob = 0x80000000u;          // buffer offset past every record: reads 0
 static_assert(kMaxSpread <= kChunk && (kChunk & (kChunk - 1)) == 0, "ring geometry");
-static_assert(3 * kChunk * kRowStride <= 160 * 1024, "LDS of one compute unit");
+static_assert(kArrays * kArrayBytes <= 160 * 1024, "LDS of one compute unit");
+static_assert(kLoadsPerChunk * (kArrays - 1) <= 63, "loads in flight fit the vmcnt field");
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+// f(std::integral_constant<int, c>) for c = 0, 1, ...: one copy of the body
+// per value, so the ring arrays are named statically in each.
+template <class F, int... c>
+__device__ __forceinline__ void for_each_c(F&& f, std::integer_sequence<int, c...>) {
+  (f(std::integral_constant<int, c>{}), ...);
+}
+
+// Wait until at most kLeft of this wave's vector-memory operations are in
+// flight (they retire in issue order).
+template <int kLeft>
+__device__ inline void vm_wait() {
+  static_assert(kLeft >= 0 && kLeft < 64, "vmcnt field");
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (kLeft & 15) | ((kLeft >> 4) << 14));
+  asm volatile("" ::: "memory");
+}
 
 struct ShiftParams {
   const uint8_t* in;
@@ -56,7 +83,7 @@ struct ShiftParams {
   int e_begin, e_count;   // the elements whose delays this launch carries
   int strips;             // row strips per channel
   int blocks;             // 256-element blocks of this launch
-  int aligned;            // n % 4 == 0 and 4-byte aligned in and out: dword access
+  int aligned;            // ring form possible: 16-byte rows, dword stores
   uint16_t delay[kShiftGroupElems];
 };
 
@@ -68,19 +95,13 @@ __device__ inline void ring_barrier() {
   asm volatile("" ::: "memory");
 }
 
-// All of this wave's vector-memory operations (ring loads and output stores)
-// are complete.
-__device__ inline void vm_wait_all() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0); lgkmcnt and expcnt at their maximum
-  asm volatile("" ::: "memory");
-}
-
 __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
-  __shared__ __attribute__((aligned(16))) uint8_t ring0[kChunk * kRowStride];
-  __shared__ __attribute__((aligned(16))) uint8_t ring1[kChunk * kRowStride];
-  __shared__ __attribute__((aligned(16))) uint8_t ring2[kChunk * kRowStride];
-  __shared__ int bounds[2];
+  __shared__ __attribute__((aligned(16))) uint8_t ring0[kArrayBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t ring1[kArrayBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t ring2[kArrayBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t ring3[kArrayBytes];
+  __shared__ __attribute__((aligned(16))) uint8_t ring4[kArrayBytes];
+  uint8_t* const ring[kArrays] = {ring0, ring1, ring2, ring3, ring4};
   const int tid = (int)threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int b = (int)(blockIdx.x % (unsigned)p.blocks);
@@ -94,18 +115,23 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
   const int64_t n = p.n;
   const int first_row = p.max_delay + p.t0 + s0;       // input row of output row s0, delay 0
 
-  // spread of this block's delays
-  if (tid == 0) {
-    bounds[0] = 0x7fffffff;
-    bounds[1] = -1;
+  // spread of this block's delays: each wave reduces all 256 (4 per lane)
+  // across its lanes, so every wave holds the same bounds without LDS
+  int dmin = 0x7fffffff, dmax = -1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (4 * lane + k < ne) {
+      dmin = min(dmin, (int)p.delay[eb + 4 * lane + k]);
+      dmax = max(dmax, (int)p.delay[eb + 4 * lane + k]);
+    }
   }
-  __syncthreads();
-  if (tid < ne) {
-    atomicMin(&bounds[0], (int)p.delay[eb + tid]);
-    atomicMax(&bounds[1], (int)p.delay[eb + tid]);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    dmin = min(dmin, __shfl_xor(dmin, m));
+    dmax = max(dmax, __shfl_xor(dmax, m));
   }
-  __syncthreads();
-  const int dmin = bounds[0], dmax = bounds[1];
+  dmin = __builtin_amdgcn_readfirstlane(dmin);
+  dmax = __builtin_amdgcn_readfirstlane(dmax);
   const int spread = dmax - dmin;
   const int e4 = eb + 4 * lane;                        // this lane's first element (launch-relative)
   const bool quad = 4 * lane < ne;                     // the lane has elements in this block
@@ -116,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
   if (p.aligned && spread <= kMaxSpread) {
     // relative input row r is input row base_row + r of the channel, for
     // r in [0, ns + spread); segment r / kChunk of the strip lives in ring
-    // array (r / kChunk) % 3
+    // array (r / kChunk) % kArrays
     const int base_row = first_row - dmax;
     const int rows = ns + spread;
     const int64_t col0 = p.e_begin + eb;               // absolute element of the block
@@ -124,31 +150,37 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(src + (int64_t)base_row * n + col0), 0,
         bytes > 0x7fffffff ? 0x7fffffff : (int)bytes, 0x00020000);
-    const uint32_t voff = quad ? (uint32_t)(4 * lane) : kOob;
     // Waves 0-3 load the ring, waves 4-7 gather from it and store. Loads and
     // stores share one counter of outstanding vector-memory operations, so a
     // wave that did both would wait for its stores whenever it waits for its
     // loads; split this way the loaders wait for loads only and the
     // gatherers never wait on memory.
-    const bool loader = wave < kWaves / 2;
-    const int rw = loader ? wave : wave - kWaves / 2;   // index within the role
-    constexpr int kRole = kWaves / 2;
-    // segment k's rows [k * kChunk, (k + 1) * kChunk) that the strip uses;
-    // loader wave rw loads rows rw, rw + 4, ... of it
+    const bool loader = wave < kLoaders;
+    const int rw = loader ? wave : wave - kLoaders;     // index within the role
+    // a 16-byte load: lane l carries row r0 + l / 16, bytes 16 (l % 16) ..
+    const int lr = lane >> 4, lc = 16 * (lane & 15);
+    const uint32_t voff = lc < ne ? (uint32_t)(lr * n + lc) : kOob;
+    // segment k: rows [k * kChunk, (k + 1) * kChunk); loader wave rw loads
+    // rows 4 (rw + 4 i) .. 4 (rw + 4 i) + 3. Every wave issues the same number
+    // of loads per segment, so a count of loads in flight names the segments
+    // still arriving: a load of rows the strip does not use reads past the
+    // record (nothing from HBM).
     auto load_seg = [&](uint8_t* seg, int k) {
-      const int lo = k * kChunk, hi = min(lo + kChunk, rows);
-      for (int r = lo + rw; r < hi; r += kRole)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_ptr)(seg + (r - lo) * kRowStride),
-                                                 4, voff + (uint32_t)r * (uint32_t)n, 0, 0, 0);
+      const int lo = k * kChunk;
+#pragma unroll
+      for (int i = 0; i < kLoadsPerChunk; ++i) {
+        const int r0 = lo + kRowsPerLoad * (rw + kLoaders * i);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (lds_void_ptr)(seg + (r0 - lo) * kRowBytes), 16,
+            r0 < rows ? voff + (uint32_t)r0 * (uint32_t)n : kOob, 0, 0, 0);
+      }
     };
     uint32_t* out = reinterpret_cast<uint32_t*>(dst + (int64_t)s0 * n + p.e_begin + e4);
-    // output rows of chunk k read input rows [k * kChunk, (k + 1) * kChunk +
-    // spread): segments k (cur) and k + 1 (nxt)
     // Element q's byte of output row s sits in input row rr = s - k * kChunk +
     // back[q] of the two segments, in [0, 2 * kChunk). Both arrays are read at
     // the same offset and the value is selected afterwards: a read through a
     // pointer chosen at run time carries no alias scope, and the compiler
-    // would then wait for the loads into the third array before it. The empty
+    // would then wait for the loads into the other arrays before it. The empty
     // asm statements keep the compiler from folding the two reads back into
     // one; they cover four rows at a time, so 32 reads are in flight before
     // the wave waits for them.
@@ -156,14 +188,14 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
     auto gather = [&](const uint8_t* cur, const uint8_t* nxt, int k) {
       if (!quad) return;
       const int end = min(ns, (k + 1) * kChunk);
-      for (int s = k * kChunk + rw; s < end; s += kRows * kRole) {
+      for (int s = k * kChunk + rw; s < end; s += kRows * kLoaders) {
         uint32_t a[kRows][4], b[kRows][4];
 #pragma unroll
         for (int j = 0; j < kRows; ++j)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int rr = s + j * kRole - k * kChunk + back[q];
-            const int at = (rr & (kChunk - 1)) * kRowStride + 4 * lane + q;
+            const int rr = s + j * kLoaders - k * kChunk + back[q];
+            const int at = (rr & (kChunk - 1)) * kRowBytes + 4 * lane + q;
             a[j][q] = cur[at];
             b[j][q] = nxt[at];
           }
@@ -177,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
                      "+v"(b[3][0]), "+v"(b[3][1]), "+v"(b[3][2]), "+v"(b[3][3]));
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
-          const int sj = s + j * kRole;
+          const int sj = s + j * kLoaders;
           if (sj >= end) break;
           uint32_t w = 0;
 #pragma unroll
@@ -187,32 +219,34 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
         }
       }
     };
-    // Step k: the loaders' rows so far (segments up to k + 1) are in, then
-    // at the barrier everyone's are and chunk k - 1 is read; the loaders load
-    // segment k + 2 into the array chunk k - 1 read while the gatherers
-    // gather chunk k. Each array is its own variable and every step names its
-    // arrays statically, so the compiler sees that the gather's reads cannot
-    // touch the array being loaded and does not wait for those loads.
-    auto step = [&](const uint8_t* cur, const uint8_t* nxt, uint8_t* ld, int k) {
-      if (loader) vm_wait_all();
-      ring_barrier();
-      if (loader)
-        load_seg(ld, k + 2);
-      else
-        gather(cur, nxt, k);
-    };
-    if (loader) {
-      load_seg(ring0, 0);
-      load_seg(ring1, 1);
-    }
+    // Step k: the loaders' segments up to k + 1 are in (at most the loads of
+    // segments k + 2 and k + 3 in flight), then at the barrier everyone's are
+    // and chunk k - 1 is read; the loaders load segment k + 4 into the array
+    // chunk k - 1 read first while the gatherers gather chunk k. Each array
+    // is its own variable and every step names its arrays statically, so the
+    // compiler sees that the gather's reads cannot touch the arrays being
+    // loaded and does not wait for those loads.
     const int nchunks = (ns + kChunk - 1) / kChunk;
-    for (int k = 0; k < nchunks; k += 3) {
-      step(ring0, ring1, ring2, k);
-      if (k + 1 < nchunks) step(ring1, ring2, ring0, k + 1);
-      if (k + 2 < nchunks) step(ring2, ring0, ring1, k + 2);
+    if (loader)
+      for_each_c([&](auto cc) { load_seg(ring[decltype(cc)::value], decltype(cc)::value); },
+                 std::make_integer_sequence<int, kArrays - 1>{});
+    for (int k0 = 0; k0 < nchunks; k0 += kArrays) {
+      for_each_c(
+          [&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            const int k = k0 + c;
+            if (k >= nchunks) return;
+            if (loader) vm_wait<2 * kLoadsPerChunk>();
+            ring_barrier();
+            if (loader)
+              load_seg(ring[(c + kArrays - 1) % kArrays], k + kArrays - 1);
+            else
+              gather(ring[c], ring[(c + 1) % kArrays], k);
+          },
+          std::make_integer_sequence<int, kArrays>{});
     }
     // no load into LDS may land after the workgroup ends
-    if (loader) vm_wait_all();
+    if (loader) vm_wait<0>();
     return;
   }
   // direct form: every byte from HBM
@@ -253,10 +287,12 @@ hipError_t launch_shift(const uint8_t* in, uint8_t* out, int n, int f, int t_in,
   p.e_count = e_count;
   p.strips = (tc + kStripRows - 1) / kStripRows;
   p.blocks = (e_count + kBlockElems - 1) / kBlockElems;
-  // the ring form addresses a strip's rows with 32-bit offsets
-  p.aligned = n % 4 == 0 && reinterpret_cast<uintptr_t>(in) % 4 == 0 &&
+  // the ring form loads 16-byte pieces of rows (every row of a block must
+  // start on a 16-byte boundary), stores dwords and addresses a strip's rows
+  // with 32-bit offsets
+  p.aligned = n % 16 == 0 && e_begin % 16 == 0 && reinterpret_cast<uintptr_t>(in) % 16 == 0 &&
               reinterpret_cast<uintptr_t>(out) % 4 == 0 &&
-              (int64_t)(kStripRows + kMaxSpread + kChunk) * n < ((int64_t)1 << 31);
+              (int64_t)(kStripRows + kMaxSpread + kArrays * kChunk) * n < ((int64_t)1 << 31);
   for (int k = 0; k < kShiftGroupElems; ++k) {
     const int d = k < e_count ? delays[e_begin + k] : 0;
     if (d < 0 || d > max_delay) return hipErrorInvalidValue;
