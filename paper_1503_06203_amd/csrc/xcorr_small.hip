@@ -13,19 +13,19 @@
 //
 // Every wave works alone on one channel over one part of its time axis, so the
 // stage loop has no barrier:
-//   * the wave's sample rows stream from HBM into a ring of 8 steps of 16
-//     samples held in registers (4 dword loads per step, 64 bytes per sample
-//     row), 8 steps ahead of use; each step is written to the wave's own
-//     1 KiB slot in LDS just before it is read. The compiler tracks each
-//     register load exactly, so a step waits only for its own loads. (Loads
-//     straight into an LDS ring would make the compiler wait for every load
-//     in flight before a read wherever it cannot tell which ring slot a load
-//     writes, which is at least once per loop iteration.)
+//   * the wave's sample rows stream from HBM into its own ring of 16 steps of
+//     16 samples in LDS (4 dword loads per step straight into LDS, 64 bytes
+//     per sample row), 15 steps ahead of use: 120 KiB of loads in flight per
+//     compute unit, enough to cover HBM latency at the full stream rate. A
+//     step waits for its own loads only (the loads retire in order).
 //   * one ds_read_b64_tr_b8 per block and step hands each lane the 8 samples of
 //     one element that its MFMA operand needs: lanes 0-31 elements 32b .. 32b+31
 //     at samples 0-7 of the step, lanes 32-63 the same elements at samples 8-15.
 //     The lane decodes them in registers into the operand itself
 //     [uRe g, uRe g+1, uIm g, uIm g+1]; nothing decoded goes back to LDS.
+//     These reads are written as inline assembly that waits for its own
+//     results: the compiler cannot tell which ring slot an LDS read touches
+//     and would otherwise wait for every load in flight before each one.
 // A workgroup of 8 waves holds C channels x S parts of the time axis
 // (C x S = 8, chosen so the launch fills the compute units). The parts of one
 // channel combine in order: part 0 writes (or adds to) the output, then after a
@@ -54,20 +54,12 @@ constexpr int kMaxElems = 64;
 constexpr int kStep = 16;                      // samples per MFMA step
 constexpr int kRow = 64;                       // LDS bytes per staged sample row
 constexpr int kStepBytes = kStep * kRow;       // 1 KiB
-constexpr int kAhead = 8;                      // steps loaded ahead of the one in use
+constexpr int kRing = 16;                      // steps in a wave's LDS ring
 constexpr int kLoadsPerStep = kStepBytes / 256;   // one dword per lane fills 256 bytes
-constexpr int kWaveBytes = kStepBytes;         // the wave's LDS slot: one step
+constexpr int kWaveBytes = kRing * kStepBytes; // the wave's LDS ring: 16 KiB
 constexpr uint32_t kOob = 0x80000000u;         // offset past every record: the load returns 0
-static_assert(kLoadsPerStep * kAhead <= 63, "outstanding loads fit the vmcnt field");
+static_assert(kLoadsPerStep * (kRing - 1) <= 63, "outstanding loads fit the vmcnt field");
 static_assert(kWaves * kWaveBytes <= 160 * 1024, "LDS of one compute unit");
-
-// f(std::integral_constant<int, c>) for c = 0, 1, ...: one copy of the body
-// per value, so c is a constant in each (registers of the ring are then
-// addressed statically).
-template <class F, int... c>
-__device__ __forceinline__ void for_each_c(F&& f, std::integer_sequence<int, c...>) {
-  (f(std::integral_constant<int, c>{}), ...);
-}
 
 struct SmallParams {
   const uint8_t* in;
@@ -100,34 +92,39 @@ __device__ __forceinline__ void small_run(const SmallParams& p, uint8_t* ring_al
   const int total = p.t_end - p.t0;
   const int s0 = min(total, part * p.steps_per_part * kStep);
   const int s1 = min(total, s0 + p.steps_per_part * kStep);
-  // whole laps of the register ring: steps past the part's end load past the
-  // record count, read 0x00 bytes and add nothing
-  const int nsteps = live ? ((s1 - s0 + kStep - 1) / kStep + kAhead - 1) / kAhead * kAhead : 0;
+  const int nsteps = live ? (s1 - s0 + kStep - 1) / kStep : 0;
 
-  // ---- loads: step k is rows [s0 + 16k, s0 + 16k + 16) of the part, four
-  // instructions of four rows each (lane l: row l / 16, elements 4 (l % 16)).
-  // Rows past s1 lie past the descriptor's record count and elements past n
-  // use an offset past every record; both read 0x00, whose fields add nothing.
+  // ---- loads: the k-th step a wave takes is rows [s0 + 16k', s0 + 16k' + 16)
+  // of the part, k' = (k + rot) mod nsteps, four instructions of four rows
+  // each (lane l: row l / 16, elements 4 (l % 16)), into ring slot k % kRing
+  // at 256 bytes per instruction. Rows past s1 lie past the descriptor's
+  // record count and elements past n use an offset past every record; both
+  // read 0x00, whose fields add nothing. The fetches for k >= nsteps (issued
+  // so that every step has the same count of loads after it) have no
+  // records and read nothing from memory.
   const uint32_t voff = (4 * (lane & 15) < n) ? (uint32_t)((lane >> 4) * ss + 4 * (lane & 15)) : kOob;
-  auto fetch = [&](int k, uint32_t (&r)[kLoadsPerStep]) {
-    const int first = p.t0 + s0 + k * kStep;     // uniform
+  // Each wave walks its steps from a starting step of its own and wraps
+  // around (the sums do not depend on the order). Channels and parts start on
+  // large power-of-two strides; walked in lockstep from their first steps,
+  // all the streams of the launch would hit the same HBM channels at once.
+  const int rot =
+      nsteps > 0 ? (int)(((unsigned)(ch * kWaves + part) * 2654435761u >> 8) % (unsigned)nsteps)
+                 : 0;
+  auto fetch = [&](int k) {
+    int kk = k + rot;                             // the step's place in the part
+    if (kk >= nsteps) kk -= nsteps;
+    const int first = k < nsteps ? p.t0 + s0 + kk * kStep : p.t0 + s1;   // uniform
     const int stop = p.t0 + s1;
     const int64_t bytes = stop > first ? (int64_t)(stop - first - 1) * ss + n : 0;
     const int records = bytes <= 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : (int)bytes);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(chan + (int64_t)(stop > first ? first : 0) * ss), 0, records,
         0x00020000);
+    uint8_t* const slot = ring + (k % kRing) * kStepBytes;
 #pragma unroll
     for (int q = 0; q < kLoadsPerStep; ++q)
-      r[q] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, voff + (uint32_t)(4 * q * ss),
-                                                                 0, 0);
-  };
-  // a step's rows into the wave's LDS slot, in the layout the loads had
-  // (instruction q: rows 4q .. 4q+3, 64 bytes each)
-  auto put = [&](const uint32_t (&r)[kLoadsPerStep]) {
-#pragma unroll
-    for (int q = 0; q < kLoadsPerStep; ++q)
-      *reinterpret_cast<uint32_t*>(ring + q * 256 + 4 * lane) = r[q];
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (tri::lds_void_ptr)(slot + q * 256), 4,
+                                               voff + (uint32_t)(4 * q * ss), 0, 0, 0);
   };
 
   // ---- operands: lane (l32, half) reads 8 rows (samples 8 half ..) of its
@@ -135,8 +132,22 @@ __device__ __forceinline__ void small_run(const SmallParams& p, uint8_t* ring_al
   // first 8 elements and the odd lanes those of the next 8.
   const int lq = lane & 15, grp = lane >> 4;
   const int tr_off = (8 * (grp >> 1) + (lq >> 1)) * kRow + 16 * (grp & 1) + 8 * (lq & 1);
-  auto tr_read = [&](int b) {
-    return __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i_ptr)(ring + tr_off + 32 * b));
+  // the transposing reads of step k's slot, complete on return
+  auto tr_read = [&](int k, v2i* raw) {
+    const uint32_t a = (uint32_t)(uintptr_t)(tri::lds_void_ptr)(ring + (k % kRing) * kStepBytes +
+                                                                  tr_off);
+    if constexpr (kNB == 1) {
+      asm volatile("ds_read_b64_tr_b8 %0, %1\n\ts_waitcnt lgkmcnt(0)"
+                   : "=&v"(raw[0])
+                   : "v"(a)
+                   : "memory");
+    } else {
+      asm volatile(
+          "ds_read_b64_tr_b8 %0, %2\n\tds_read_b64_tr_b8 %1, %2 offset:32\n\ts_waitcnt lgkmcnt(0)"
+          : "=&v"(raw[0]), "=&v"(raw[kNB - 1])
+          : "v"(a)
+          : "memory");
+    }
   };
   uint32_t sum_re[kNB], sum_im[kNB];
   v16i acc_re[kPairs], acc_im[kPairs];
@@ -168,42 +179,26 @@ __device__ __forceinline__ void small_run(const SmallParams& p, uint8_t* ring_al
       }
   };
 
-  // ---- stream: step k's rows sit in regs[k % kAhead]. Every step issues the
-  // loads of step k + kAhead into the registers step k has vacated (past the
-  // part's end they read nothing), writes step k + 1 to the LDS slot (the
-  // compiler waits for exactly those loads) and requests its transposing
-  // reads, then multiplies step k. LDS operations of a wave run in order, so
-  // the next step's writes follow this step's reads of the slot.
+  // ---- stream: every step first issues the loads of step k + kRing - 1 into
+  // the slot step k - 1 has vacated, then waits until only the loads issued
+  // after step k's are in flight, reads its slot and multiplies.
   if (nsteps > 0) {
-    uint32_t regs[kAhead][kLoadsPerStep];
-    v2i cur[kNB], nxt[kNB];
-    for_each_c([&](auto cc) { fetch(decltype(cc)::value, regs[decltype(cc)::value]); },
-               std::make_integer_sequence<int, kAhead>{});
-    put(regs[0]);
-#pragma unroll
-    for (int b = 0; b < kNB; ++b) cur[b] = tr_read(b);
+    for (int k = 0; k < kRing - 1; ++k) fetch(k);
 #pragma unroll 1
-    for (int k0 = 0; k0 < nsteps; k0 += kAhead) {
-      for_each_c(
-          [&](auto cc) {
-            constexpr int c = decltype(cc)::value;
-            fetch(k0 + c + kAhead, regs[c]);
-            put(regs[(c + 1) % kAhead]);
-#pragma unroll
-            for (int b = 0; b < kNB; ++b) nxt[b] = tr_read(b);
-            step(cur);
-#pragma unroll
-            for (int b = 0; b < kNB; ++b) cur[b] = nxt[b];
-          },
-          std::make_integer_sequence<int, kAhead>{});
+    for (int k = 0; k < nsteps; ++k) {
+      fetch(k + kRing - 1);
+      vm_wait<kLoadsPerStep * (kRing - 1)>();
+      v2i raw[kNB];
+      tr_read(k, raw);
+      step(raw);
     }
-    vm_wait<0>();
   }
+  // no load into LDS may land after the ring is reused or the workgroup ends
+  vm_wait<0>();
 
   // ---- offset corrections: the two lane halves hold the field sums of the
   // same element over complementary samples
   uint32_t* const cor = reinterpret_cast<uint32_t*>(ring);   // [cr, ci_row, ci_col][64]
-  __builtin_amdgcn_s_waitcnt(0xC07F);   // this wave's LDS reads are done before the ring is reused
 #pragma unroll
   for (int b = 0; b < kNB; ++b) {
     const uint32_t sr = sum_re[b] + (uint32_t)__shfl_xor((int)sum_re[b], 32);
