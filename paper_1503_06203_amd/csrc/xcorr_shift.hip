@@ -56,7 +56,7 @@ static_assert(kLoadsPerChunk * (kArrays - 1) <= 63, "loads in flight fit the vmc
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
 // f(std::integral_constant<int, c>) for c = 0, 1, ...: one copy of the body
-// per value, so the ring arrays are named statically in each.
+// per value, so c is a constant in each.
 template <class F, int... c>
 __device__ __forceinline__ void for_each_c(F&& f, std::integer_sequence<int, c...>) {
   (f(std::integral_constant<int, c>{}), ...);
@@ -96,12 +96,7 @@ __device__ inline void ring_barrier() {
 }
 
 __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
-  __shared__ __attribute__((aligned(16))) uint8_t ring0[kArrayBytes];
-  __shared__ __attribute__((aligned(16))) uint8_t ring1[kArrayBytes];
-  __shared__ __attribute__((aligned(16))) uint8_t ring2[kArrayBytes];
-  __shared__ __attribute__((aligned(16))) uint8_t ring3[kArrayBytes];
-  __shared__ __attribute__((aligned(16))) uint8_t ring4[kArrayBytes];
-  uint8_t* const ring[kArrays] = {ring0, ring1, ring2, ring3, ring4};
+  __shared__ __attribute__((aligned(16))) uint8_t ring[kArrays * kArrayBytes];
   const int tid = (int)threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int b = (int)(blockIdx.x % (unsigned)p.blocks);
@@ -176,45 +171,48 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
       }
     };
     uint32_t* out = reinterpret_cast<uint32_t*>(dst + (int64_t)s0 * n + p.e_begin + e4);
-    // Element q's byte of output row s sits in input row rr = s - k * kChunk +
-    // back[q] of the two segments, in [0, 2 * kChunk). Both arrays are read at
-    // the same offset and the value is selected afterwards: a read through a
-    // pointer chosen at run time carries no alias scope, and the compiler
-    // would then wait for the loads into the other arrays before it. The empty
-    // asm statements keep the compiler from folding the two reads back into
-    // one; they cover four rows at a time, so 32 reads are in flight before
-    // the wave waits for them.
-    constexpr int kRows = 4;
-    auto gather = [&](const uint8_t* cur, const uint8_t* nxt, int k) {
+    // Element q's byte of output row s sits in relative input row
+    // rr = s - k * kChunk + back[q] of segments k and k + 1, in [0, 2 * kChunk):
+    // array (c + rr / kChunk) % kArrays, row rr % kChunk, for c = k % kArrays.
+    // The reads are inline assembly that waits for its own results (16 reads,
+    // four rows, per wait): the compiler cannot tell which array a read
+    // touches and would otherwise wait for every load in flight before each.
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(lds_void_ptr)ring + 4 * lane;
+    auto gather = [&](int c, int k) {
       if (!quad) return;
       const int end = min(ns, (k + 1) * kChunk);
-      for (int s = k * kChunk + rw; s < end; s += kRows * kLoaders) {
-        uint32_t a[kRows][4], b[kRows][4];
+      for (int s = k * kChunk + rw; s < end; s += 4 * kLoaders) {
+        uint32_t at[4][4], v[4][4];
 #pragma unroll
-        for (int j = 0; j < kRows; ++j)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int rr = s + j * kLoaders - k * kChunk + back[q];
-            const int at = (rr & (kChunk - 1)) * kRowBytes + 4 * lane + q;
-            a[j][q] = cur[at];
-            b[j][q] = nxt[at];
+            int seg = c + (rr >> 7);
+            if (seg >= kArrays) seg -= kArrays;
+            at[j][q] = lds0 + (uint32_t)(seg * kArrayBytes + (rr & (kChunk - 1)) * kRowBytes + q);
           }
-        asm volatile("" : "+v"(a[0][0]), "+v"(a[0][1]), "+v"(a[0][2]), "+v"(a[0][3]),
-                     "+v"(a[1][0]), "+v"(a[1][1]), "+v"(a[1][2]), "+v"(a[1][3]),
-                     "+v"(a[2][0]), "+v"(a[2][1]), "+v"(a[2][2]), "+v"(a[2][3]),
-                     "+v"(a[3][0]), "+v"(a[3][1]), "+v"(a[3][2]), "+v"(a[3][3]));
-        asm volatile("" : "+v"(b[0][0]), "+v"(b[0][1]), "+v"(b[0][2]), "+v"(b[0][3]),
-                     "+v"(b[1][0]), "+v"(b[1][1]), "+v"(b[1][2]), "+v"(b[1][3]),
-                     "+v"(b[2][0]), "+v"(b[2][1]), "+v"(b[2][2]), "+v"(b[2][3]),
-                     "+v"(b[3][0]), "+v"(b[3][1]), "+v"(b[3][2]), "+v"(b[3][3]));
+        asm volatile(
+            "ds_read_u8 %0, %16\n\tds_read_u8 %1, %17\n\tds_read_u8 %2, %18\n\t"
+            "ds_read_u8 %3, %19\n\tds_read_u8 %4, %20\n\tds_read_u8 %5, %21\n\t"
+            "ds_read_u8 %6, %22\n\tds_read_u8 %7, %23\n\tds_read_u8 %8, %24\n\t"
+            "ds_read_u8 %9, %25\n\tds_read_u8 %10, %26\n\tds_read_u8 %11, %27\n\t"
+            "ds_read_u8 %12, %28\n\tds_read_u8 %13, %29\n\tds_read_u8 %14, %30\n\t"
+            "ds_read_u8 %15, %31\n\ts_waitcnt lgkmcnt(0)"
+            : "=&v"(v[0][0]), "=&v"(v[0][1]), "=&v"(v[0][2]), "=&v"(v[0][3]), "=&v"(v[1][0]),
+              "=&v"(v[1][1]), "=&v"(v[1][2]), "=&v"(v[1][3]), "=&v"(v[2][0]), "=&v"(v[2][1]),
+              "=&v"(v[2][2]), "=&v"(v[2][3]), "=&v"(v[3][0]), "=&v"(v[3][1]), "=&v"(v[3][2]),
+              "=&v"(v[3][3])
+            : "v"(at[0][0]), "v"(at[0][1]), "v"(at[0][2]), "v"(at[0][3]), "v"(at[1][0]),
+              "v"(at[1][1]), "v"(at[1][2]), "v"(at[1][3]), "v"(at[2][0]), "v"(at[2][1]),
+              "v"(at[2][2]), "v"(at[2][3]), "v"(at[3][0]), "v"(at[3][1]), "v"(at[3][2]),
+              "v"(at[3][3])
+            : "memory");
 #pragma unroll
-        for (int j = 0; j < kRows; ++j) {
+        for (int j = 0; j < 4; ++j) {
           const int sj = s + j * kLoaders;
           if (sj >= end) break;
-          uint32_t w = 0;
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            w |= (sj - k * kChunk + back[q] < kChunk ? a[j][q] : b[j][q]) << (8 * q);
+          const uint32_t w = v[j][0] | (v[j][1] << 8) | (v[j][2] << 16) | (v[j][3] << 24);
           *reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(out) + (int64_t)sj * n) = w;
         }
       }
@@ -222,14 +220,10 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
     // Step k: the loaders' segments up to k + 1 are in (at most the loads of
     // segments k + 2 and k + 3 in flight), then at the barrier everyone's are
     // and chunk k - 1 is read; the loaders load segment k + 4 into the array
-    // chunk k - 1 read first while the gatherers gather chunk k. Each array
-    // is its own variable and every step names its arrays statically, so the
-    // compiler sees that the gather's reads cannot touch the arrays being
-    // loaded and does not wait for those loads.
+    // chunk k - 1 read first while the gatherers gather chunk k.
     const int nchunks = (ns + kChunk - 1) / kChunk;
     if (loader)
-      for_each_c([&](auto cc) { load_seg(ring[decltype(cc)::value], decltype(cc)::value); },
-                 std::make_integer_sequence<int, kArrays - 1>{});
+      for (int k = 0; k < kArrays - 1; ++k) load_seg(ring + k * kArrayBytes, k);
     for (int k0 = 0; k0 < nchunks; k0 += kArrays) {
       for_each_c(
           [&](auto cc) {
@@ -239,9 +233,9 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
             if (loader) vm_wait<2 * kLoadsPerChunk>();
             ring_barrier();
             if (loader)
-              load_seg(ring[(c + kArrays - 1) % kArrays], k + kArrays - 1);
+              load_seg(ring + ((c + kArrays - 1) % kArrays) * kArrayBytes, k + kArrays - 1);
             else
-              gather(ring[c], ring[(c + 1) % kArrays], k);
+              gather(c, k);
           },
           std::make_integer_sequence<int, kArrays>{});
     }
