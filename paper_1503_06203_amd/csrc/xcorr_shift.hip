@@ -174,40 +174,75 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
     // Element q's byte of output row s sits in relative input row
     // rr = s - k * kChunk + back[q] of segments k and k + 1, in [0, 2 * kChunk):
     // array (c + rr / kChunk) % kArrays, row rr % kChunk, for c = k % kArrays.
-    // The reads are inline assembly that waits for its own results (16 reads,
-    // four rows, per wait): the compiler cannot tell which array a read
-    // touches and would otherwise wait for every load in flight before each.
+    // The arrays are consecutive in the ring, so for c < kArrays - 1 both
+    // segments form one run of rows and the byte sits at
+    //   ring + c * kArrayBytes + rr * kRowBytes + 4 * lane + q:
+    // a per-lane base (delay and column) plus the row, whose part common to
+    // the wave's four rows goes into the reads' immediate offsets. Only for
+    // c = kArrays - 1 does segment k + 1 wrap to array 0. A wave gathers rows
+    // rw, rw + 4, rw + 8, rw + 12 of every 16 (as the loaders load them), so
+    // its rows lie at most 127 rows into the chunk and rr < 2 * kChunk.
+    // The reads are inline assembly that waits for its own results (16 reads
+    // per wait): the compiler cannot tell which array a read touches and would
+    // otherwise wait for every load in flight before each.
     const uint32_t lds0 = (uint32_t)(uintptr_t)(lds_void_ptr)ring + 4 * lane;
-    auto gather = [&](int c, int k) {
+    uint32_t col[4];                                   // lane's byte q, delay included
+#pragma unroll
+    for (int q = 0; q < 4; ++q) col[q] = lds0 + (uint32_t)(back[q] * kRowBytes + q);
+    auto gather = [&](auto cc, int k) {
+      constexpr int c = decltype(cc)::value;
       if (!quad) return;
       const int end = min(ns, (k + 1) * kChunk);
       for (int s = k * kChunk + rw; s < end; s += 4 * kLoaders) {
-        uint32_t at[4][4], v[4][4];
+        const uint32_t row = (uint32_t)(c * kArrayBytes + (s - k * kChunk) * kRowBytes);
+        uint32_t v[4][4];
+        if constexpr (c < kArrays - 1) {
+          const uint32_t a0 = col[0] + row, a1 = col[1] + row, a2 = col[2] + row,
+                         a3 = col[3] + row;
+          asm volatile(
+              "ds_read_u8 %0, %16\n\tds_read_u8 %1, %17\n\tds_read_u8 %2, %18\n\t"
+              "ds_read_u8 %3, %19\n\tds_read_u8 %4, %16 offset:1024\n\t"
+              "ds_read_u8 %5, %17 offset:1024\n\tds_read_u8 %6, %18 offset:1024\n\t"
+              "ds_read_u8 %7, %19 offset:1024\n\tds_read_u8 %8, %16 offset:2048\n\t"
+              "ds_read_u8 %9, %17 offset:2048\n\tds_read_u8 %10, %18 offset:2048\n\t"
+              "ds_read_u8 %11, %19 offset:2048\n\tds_read_u8 %12, %16 offset:3072\n\t"
+              "ds_read_u8 %13, %17 offset:3072\n\tds_read_u8 %14, %18 offset:3072\n\t"
+              "ds_read_u8 %15, %19 offset:3072\n\ts_waitcnt lgkmcnt(0)"
+              : "=&v"(v[0][0]), "=&v"(v[0][1]), "=&v"(v[0][2]), "=&v"(v[0][3]), "=&v"(v[1][0]),
+                "=&v"(v[1][1]), "=&v"(v[1][2]), "=&v"(v[1][3]), "=&v"(v[2][0]), "=&v"(v[2][1]),
+                "=&v"(v[2][2]), "=&v"(v[2][3]), "=&v"(v[3][0]), "=&v"(v[3][1]), "=&v"(v[3][2]),
+                "=&v"(v[3][3])
+              : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
+              : "memory");
+        } else {
+          // segment k + 1 is array 0: rows past the chunk's end move back by
+          // the whole ring
+          uint32_t at[4][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < 4; ++j)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int rr = s + j * kLoaders - k * kChunk + back[q];
-            int seg = c + (rr >> 7);
-            if (seg >= kArrays) seg -= kArrays;
-            at[j][q] = lds0 + (uint32_t)(seg * kArrayBytes + (rr & (kChunk - 1)) * kRowBytes + q);
-          }
-        asm volatile(
-            "ds_read_u8 %0, %16\n\tds_read_u8 %1, %17\n\tds_read_u8 %2, %18\n\t"
-            "ds_read_u8 %3, %19\n\tds_read_u8 %4, %20\n\tds_read_u8 %5, %21\n\t"
-            "ds_read_u8 %6, %22\n\tds_read_u8 %7, %23\n\tds_read_u8 %8, %24\n\t"
-            "ds_read_u8 %9, %25\n\tds_read_u8 %10, %26\n\tds_read_u8 %11, %27\n\t"
-            "ds_read_u8 %12, %28\n\tds_read_u8 %13, %29\n\tds_read_u8 %14, %30\n\t"
-            "ds_read_u8 %15, %31\n\ts_waitcnt lgkmcnt(0)"
-            : "=&v"(v[0][0]), "=&v"(v[0][1]), "=&v"(v[0][2]), "=&v"(v[0][3]), "=&v"(v[1][0]),
-              "=&v"(v[1][1]), "=&v"(v[1][2]), "=&v"(v[1][3]), "=&v"(v[2][0]), "=&v"(v[2][1]),
-              "=&v"(v[2][2]), "=&v"(v[2][3]), "=&v"(v[3][0]), "=&v"(v[3][1]), "=&v"(v[3][2]),
-              "=&v"(v[3][3])
-            : "v"(at[0][0]), "v"(at[0][1]), "v"(at[0][2]), "v"(at[0][3]), "v"(at[1][0]),
-              "v"(at[1][1]), "v"(at[1][2]), "v"(at[1][3]), "v"(at[2][0]), "v"(at[2][1]),
-              "v"(at[2][2]), "v"(at[2][3]), "v"(at[3][0]), "v"(at[3][1]), "v"(at[3][2]),
-              "v"(at[3][3])
-            : "memory");
+            for (int q = 0; q < 4; ++q) {
+              const int rr = s + j * kLoaders - k * kChunk + back[q];
+              at[j][q] = col[q] + row + (uint32_t)(j * kLoaders * kRowBytes) -
+                         (rr >= kChunk ? (uint32_t)(kArrays * kArrayBytes) : 0u);
+            }
+          asm volatile(
+              "ds_read_u8 %0, %16\n\tds_read_u8 %1, %17\n\tds_read_u8 %2, %18\n\t"
+              "ds_read_u8 %3, %19\n\tds_read_u8 %4, %20\n\tds_read_u8 %5, %21\n\t"
+              "ds_read_u8 %6, %22\n\tds_read_u8 %7, %23\n\tds_read_u8 %8, %24\n\t"
+              "ds_read_u8 %9, %25\n\tds_read_u8 %10, %26\n\tds_read_u8 %11, %27\n\t"
+              "ds_read_u8 %12, %28\n\tds_read_u8 %13, %29\n\tds_read_u8 %14, %30\n\t"
+              "ds_read_u8 %15, %31\n\ts_waitcnt lgkmcnt(0)"
+              : "=&v"(v[0][0]), "=&v"(v[0][1]), "=&v"(v[0][2]), "=&v"(v[0][3]), "=&v"(v[1][0]),
+                "=&v"(v[1][1]), "=&v"(v[1][2]), "=&v"(v[1][3]), "=&v"(v[2][0]), "=&v"(v[2][1]),
+                "=&v"(v[2][2]), "=&v"(v[2][3]), "=&v"(v[3][0]), "=&v"(v[3][1]), "=&v"(v[3][2]),
+                "=&v"(v[3][3])
+              : "v"(at[0][0]), "v"(at[0][1]), "v"(at[0][2]), "v"(at[0][3]), "v"(at[1][0]),
+                "v"(at[1][1]), "v"(at[1][2]), "v"(at[1][3]), "v"(at[2][0]), "v"(at[2][1]),
+                "v"(at[2][2]), "v"(at[2][3]), "v"(at[3][0]), "v"(at[3][1]), "v"(at[3][2]),
+                "v"(at[3][3])
+              : "memory");
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int sj = s + j * kLoaders;
@@ -235,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void xcorr_shift_kernel(ShiftParams p) {
             if (loader)
               load_seg(ring + ((c + kArrays - 1) % kArrays) * kArrayBytes, k + kArrays - 1);
             else
-              gather(c, k);
+              gather(cc, k);
           },
           std::make_integer_sequence<int, kArrays>{});
     }

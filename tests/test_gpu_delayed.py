@@ -202,7 +202,8 @@ def test_delayed_unaligned_input():
 @pytest.mark.parametrize("f,t,n,lo,hi", [(2, 1024, 260, 5, 5), (2, 1000, 516, 0, 1),
                                          (1, 2048, 1024, 0, 128), (2, 4096, 2048, 0, 128),
                                          (1, 640, 516, 0, 300), (3, 100, 64, 3, 90),
-                                         (1, 129, 2048, 0, 64), (2, 300, 261, 4, 4)])
+                                         (1, 129, 2048, 0, 64), (2, 300, 261, 4, 4),
+                                         (1, 2300, 1040, 10, 110)])
 def test_delayed_shift_form(f, t, n, lo, hi):
     print("shift form f=%d t=%d n=%d delays %d..%d" % (f, t, n, lo, hi), flush=True)
     rng = np.random.default_rng(f * 11 + n + hi + t)
