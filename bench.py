@@ -39,8 +39,6 @@ PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
 # kernel symbol of each library variant (the name rocprofv3 reports)
 KERNEL_OF_VARIANT = {   # first matching prefix wins
     "tile128": "xcorr_tile128_kernel",
-    "wide128x256_w4": "xcorr_wide_kernel",
-    "wide128x256_w8": "xcorr_wide8_kernel",
     "tri256_w8_bf6": "xcorr_tri_bf6_kernel",
     "tri256": "xcorr_tri_kernel",
     "rect128x256_tri256_w8_bf6": "xcorr_rect_bf6_kernel",
@@ -65,8 +63,6 @@ KERNEL_SOURCE = {
     "xcorr_tri_kernel": "xcorr_tri.hip",
     "xcorr_small_kernel": "xcorr_small.hip",
     "xcorr_tri_bf6_kernel": "xcorr_tri_bf6.hip",
-    "xcorr_wide8_kernel": "xcorr_wide.hip",
-    "xcorr_wide_kernel": "xcorr_wide.hip",
     "xcorr_tile128_kernel": "xcorr_tile.hip",
     "xcorr_shift_kernel": "xcorr_shift.hip",
     "xcorr_rect_bf6_kernel": "xcorr_rect_bf6.hip",

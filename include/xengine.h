@@ -97,8 +97,8 @@ xeng_status xeng_correlate(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
  * combined with exact int32 atomic adds). Every variant gives bit-identical
  * results. variant = -1 lets the library choose (same as xeng_correlate).
  *   0 tile128_kc64_mfma32x32x32         any n, any input alignment
- *   1 wide128x256_w4_kc64_mfma32x32x32  n % 4 == 0, 4-byte aligned input
- *   2 wide128x256_w8_kc64_mfma32x32x32  as 1, eight waves per tile
+ *   1, 2 retired (128 x 256 tiles with 4 or 8 waves, superseded by 5):
+ *     xeng_correlate_variant returns XENG_ENOTFOUND for them
  *   3 tri256_w8_kc64_mfma32x32x32       n <= 256, n % 4 == 0, aligned input
  *   4 tri256_w8_bf6_mfma32x32x64        as 3, on the f8f6f4 matrix cores: the
  *     4-bit values (Sec. III) are exact in the 6-bit float E3M2 and partial

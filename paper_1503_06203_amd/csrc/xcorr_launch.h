@@ -18,19 +18,6 @@ hipError_t launch_tile128(const uint8_t* in, int32_t* vis, int n, int f, int t, 
                           int split, bool aligned, hipStream_t stream);
 int tile128_stage_samples();
 
-// 128x256-tile MFMA kernel, one workgroup per CU. Needs n % 4 == 0 and a
-// 4-byte aligned input (dword buffer loads). Sums samples [t0, t0 + t_count)
-// of each channel (t = samples per channel); t_count is limited to
-// wide_max_samples_per_launch() so the scaled int32 sums cannot overflow.
-// waves = 4 (one wave of 64x128 per SIMD) or 8 (two waves of 64x64 per SIMD).
-// ss, cs: bytes from one sample to the next and from one channel to the next
-// (n and t * n for the dense [F][T][N] layout; multiples of 4).
-hipError_t launch_wide(const uint8_t* in, int32_t* vis, int n, int f, int t, int64_t ss,
-                       int64_t cs, int t0, int t_count, int accumulate, int split, int waves,
-                       hipStream_t stream);
-int64_t wide_max_samples_per_launch();
-int64_t wide_tiles_per_channel(int n);
-
 // Kernel for arrays of any size (n % 4 == 0, 4-byte aligned input; meant for
 // n > 256): each channel is cut into rect_units_per_channel(n) pieces, the
 // 256-element diagonal squares (the triangle kernel's block programs) and the

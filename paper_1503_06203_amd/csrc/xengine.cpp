@@ -74,13 +74,6 @@ int rect_auto_split(int n, int f, int64_t t_count, int cus) {
   return auto_split(rect_units_per_channel(n) * f, (t_count + stage - 1) / stage, cus);
 }
 
-int wide_auto_split(int n, int f, int64_t t_count, int cus) {
-  const int64_t stage = queue_stage_samples();
-  const int64_t win = wide_max_samples_per_launch();
-  const int64_t t_launch = t_count < win ? t_count : win;   // one launch window
-  return auto_split(wide_tiles_per_channel(n) * f, (t_launch + stage - 1) / stage, cus);
-}
-
 }  // namespace xeng
 
 namespace {
@@ -95,8 +88,8 @@ struct Variant {
 // Index = variant id.
 const Variant kVariants[] = {
     {"tile128_kc64_mfma32x32x32"},        // any n, any input alignment
-    {"wide128x256_w4_kc64_mfma32x32x32"}, // n % 4 == 0, 4-byte aligned input
-    {"wide128x256_w8_kc64_mfma32x32x32"}, // n % 4 == 0, 4-byte aligned input
+    {"retired_wide128x256_w4"},           // superseded by 5; refused
+    {"retired_wide128x256_w8"},           // superseded by 5; refused
     {"tri256_w8_kc64_mfma32x32x32"},      // n <= 256, n % 4 == 0, 4-byte aligned input
     {"tri256_w8_bf6_mfma32x32x64"},       // as above, on bf6 operands (exact)
     {"rect128x256_tri256_w8_kc64_mfma32x32x32"},  // n % 4 == 0, 4-byte aligned input
@@ -104,8 +97,8 @@ const Variant kVariants[] = {
     {"rect128x256_tri256_w8_bf6_mfma32x32x64"},  // as 5, on bf6 operands (exact)
 };
 constexpr int kVariantTile128 = 0;
-constexpr int kVariantWide = 1;
-constexpr int kVariantWide8 = 2;
+constexpr int kVariantRetired1 = 1;
+constexpr int kVariantRetired2 = 2;
 constexpr int kVariantTri = 3;
 constexpr int kVariantTriBf6 = 4;
 constexpr int kVariantRect = 5;
@@ -127,8 +120,6 @@ int default_variant(int n, bool aligned) {
 bool variant_fits(int v, int n, bool aligned, bool dense) {
   switch (v) {
     case kVariantTile128: return dense;
-    case kVariantWide:
-    case kVariantWide8: return aligned && (int64_t)n * 32 < ((int64_t)1 << 31);
     case kVariantRect:
     case kVariantRectBf6: return aligned;
     case kVariantTri:
@@ -252,12 +243,9 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
   if (!dense && variant == kVariantTile128)
     return fail(XENG_EINVAL, "variant %s reads the dense [F][T][N] layout only",
                 kVariants[variant].name);
-  const bool wide = variant == kVariantWide || variant == kVariantWide8;
-  if (wide && !aligned)
-    return fail(XENG_EINVAL, "variant %s needs n %% 4 == 0 and a 4-byte aligned input",
-                kVariants[variant].name);
-  if (wide && (int64_t)n * 32 >= ((int64_t)1 << 31))
-    return fail(XENG_EINVAL, "variant %s supports n < 2^26", kVariants[variant].name);
+  if (variant == kVariantRetired1 || variant == kVariantRetired2)
+    return fail(XENG_ENOTFOUND, "variant %d (%s) is retired; variant %d covers its jobs", variant,
+                kVariants[variant].name, kVariantRect);
   const bool rect = variant == kVariantRect || variant == kVariantRectBf6;
   if (rect && !aligned)
     return fail(XENG_EINVAL, "variant %s needs n %% 4 == 0 and a 4-byte aligned input",
@@ -276,8 +264,6 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
   // the bf6 kernels' fp32 sums are exact up to a bounded number of samples per part
   if (variant == kVariantTriBf6 || variant == kVariantRectBf6)
     split = std::max(split, xeng::tri_bf6_min_split(t));
-  if (variant == kVariantWide8 && split_t == 0)
-    split = xeng::wide_auto_split(n, f, t, xeng::device_cu_count());
   // the small kernel combines its time parts itself: no split, no fill
   if (small) split = 1;
   if (split > 1 && !accumulate) {
@@ -296,16 +282,6 @@ xeng_status correlate_impl(const uint8_t* d_in, int32_t* d_vis, int n, int f, in
     e = xeng::launch_rect(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
   } else if (variant == kVariantTriBf6) {
     e = xeng::launch_tri_bf6(d_in, d_vis, n, f, t, ss, cs, 0, t, accumulate, split, stream);
-  } else if (wide) {
-    // one launch per window of at most wide_max_samples_per_launch() samples;
-    // windows after the first add to what the earlier ones wrote
-    const int64_t win = xeng::wide_max_samples_per_launch();
-    for (int64_t t0 = 0; t0 < t && e == hipSuccess; t0 += win) {
-      const int cnt = (int)std::min<int64_t>(win, t - t0);
-      const int acc = (t0 == 0) ? accumulate : 1;
-      e = xeng::launch_wide(d_in, d_vis, n, f, t, ss, cs, (int)t0, cnt, acc, split,
-                            variant == kVariantWide8 ? 8 : 4, stream);
-    }
   } else {
     e = xeng::launch_tile128(d_in, d_vis, n, f, t, accumulate, split, aligned, stream);
   }
@@ -584,7 +560,6 @@ xeng_status xeng_choose_variant(int n, int f, int t, int input_aligned, int* var
   const int cus = xeng::device_cu_count();
   int split = 1;
   if (t > 0 && (v == kVariantTri || v == kVariantTriBf6)) split = xeng::tri_auto_split(f, t, cus);
-  if (t > 0 && v == kVariantWide8) split = xeng::wide_auto_split(n, f, t, cus);
   if (t > 0 && (v == kVariantRect || v == kVariantRectBf6))
     split = xeng::rect_auto_split(n, f, t, cus);
   if (ts > 0) split = ts;

@@ -26,9 +26,8 @@ int device_cu_count();
 // channels) over `stages` stages, chosen to fill `cus` compute units in whole
 // rounds.
 int auto_split(int64_t units, int64_t stages, int cus);
-// The split for the triangle kernel and for the 8-wave wide kernel.
+// The split for the triangle kernel and for the squares-and-tiles kernel.
 int tri_auto_split(int f, int64_t t_count, int cus);
-int wide_auto_split(int n, int f, int64_t t_count, int cus);
 int rect_auto_split(int n, int f, int64_t t_count, int cus);
 // The autotuner's choice for this job class on the current device, if any
 // (variant id, split_t as xeng_correlate_variant takes it: 0 = the variant's own).

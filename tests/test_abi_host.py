@@ -89,6 +89,9 @@ def test_range_guard(lib):
 
 def test_unknown_variant(lib):
     assert call(lib, variant=lib.xeng_variant_count()) == ENOTFOUND
+    # the retired 128 x 256 wide kernels are refused (variant 5 covers them)
+    assert call(lib, variant=1) == ENOTFOUND and call(lib, variant=2) == ENOTFOUND
+    assert lib.xeng_variant_name(1).startswith(b"retired")
     assert lib.xeng_variant_name(-5) is None
     assert lib.xeng_variant_name(0) is not None
 
@@ -195,14 +198,16 @@ def test_tune_table_host(lib, tmp_path):
     default_t5000 = xe.choose_variant(300, 2, 5000)
     default_f3 = xe.choose_variant(300, 3, 3000)
     cache = tmp_path / "tune.txt"
-    cache.write_text("xeng-tune none 300 2 11 2 4 1.5\n"      # wide8, split 4, t in [2048, 4096)
+    cache.write_text("xeng-tune none 300 2 11 7 4 1.5\n"      # rect bf6, split 4, t in [2048, 4096)
                      "xeng-tune gfx000 300 2 11 0 1 1.0\n"    # another device: skipped
                      "garbage line\n"
-                     "xeng-tune none 300 2 11 1 2 1.2\n"      # a later line replaces the first
-                     "xeng-tune none 64 1 8 3 0 0.1\n")       # tri256 with its own split
-    assert xe.tune_load(cache) == 3
+                     "xeng-tune none 300 2 11 0 2 1.2\n"      # a later line replaces the first
+                     "xeng-tune none 64 1 8 3 0 0.1\n"        # tri256 with its own split
+                     "xeng-tune none 512 2 11 1 1 0.9\n")     # a retired variant: never used
+    assert xe.tune_load(cache) == 4
     v, split, name = xe.choose_variant(300, 2, 3000)
-    assert (v, split) == (1, 2) and name.startswith("wide128x256_w4")
+    assert (v, split) == (0, 2) and name.startswith("tile128")
+    assert xe.choose_variant(512, 2, 3000)[2].startswith("rect128x256")
     assert xe.choose_variant(300, 2, 5000) == default_t5000            # other t bucket
     assert xe.choose_variant(300, 3, 3000) == default_f3               # other f
     # a tuned variant that cannot run the call (unaligned input) is not used

@@ -154,7 +154,7 @@ RECT_BF6_VARIANT = 7
 RECT_VARIANTS = [RECT_VARIANT, RECT_BF6_VARIANT]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [0, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("f,t,n", VARIANT_SHAPES)
 def test_each_variant_matches_oracle(variant, f, t, n):
     x = synth.quantized_gaussian(f, t, n, 3.0, seed=f * 7919 + t * 31 + n)
@@ -242,19 +242,9 @@ def test_tri_bf6_fp32_range(t):
     assert (vis[..., 0] == 128 * t).all() and (vis[..., 1] == 0).all()
 
 
-@pytest.mark.parametrize("variant", [1, 2])
-@pytest.mark.parametrize("split", [2, 5])
-def test_wide_variant_time_split(variant, split):
-    x = synth.quantized_gaussian(1, 1500, 512, 2.5, seed=split + 40)
-    xd = x.to(DEV)
-    ref = gpu_correlate(xd, variant=0, split=1)
-    got = gpu_correlate(xd, variant=variant, split=split)
-    assert torch.equal(ref, got)
-    assert_same(got, oracle.correlate(x.numpy()))
-
-
 def test_long_integration_windows():
-    # T above one launch window of the wide kernel (2^20 - 64 samples)
+    # T above 2^20 samples: parts of the time axis that each stay far below
+    # the int32 range of one workgroup's sums
     x = synth.quantized_gaussian(1, 1_100_000, 64, 2.5, seed=77)
     full_check(x)
 
