@@ -137,6 +137,33 @@ def _delayed(rng, seed):
     assert_same(vis, oracle.correlate_delayed(x.numpy(), delays), str(case))
 
 
+def _delayed_shift(rng, seed):
+    # the shift form: n above 256 or t not whole 64-sample stages; n % 16 == 0
+    # half the time (the ring form), a workspace of a few windows a third of
+    # the time
+    import paper_1503_06203_amd as xe
+    n = int(rng.integers(257, 600)) if rng.random() < 0.7 else int(rng.integers(1, 257))
+    if rng.random() < 0.5:
+        n = max(16, n - n % 16)
+    f, t = int(rng.integers(1, 3)), int(rng.integers(1, 1300))
+    if n <= 256 and t % 64 == 0:
+        t += 1
+    spread = int(rng.choice([0, 1, 37, 128, 129, 400]))
+    delays = int(rng.integers(0, 30)) + rng.integers(0, spread + 1, n)
+    windows = rng.random() < 0.35
+    case = ("delayed-shift", f, t, n, spread, windows)
+    print(case, flush=True)
+    x = _gen(rng, f, t + int(delays.max()), n, seed)
+    vis = xe.new_vis(n, f)
+    vis.fill_(4)
+    ws = None
+    if windows:
+        ws = torch.empty(f * n * 128 * int(rng.integers(1, 4)) + 3, dtype=torch.uint8, device=DEV)
+    xe.correlate_delayed(x.to(DEV), vis, delays, workspace=ws)
+    torch.cuda.synchronize()
+    assert_same(vis, oracle.correlate_delayed(x.numpy(), delays), str(case))
+
+
 def _plan(rng, seed):
     # one persistent launch over a few jobs, some accumulating onto held sums
     import paper_1503_06203_amd as xe
@@ -167,7 +194,7 @@ def _plan(rng, seed):
 @pytest.mark.parametrize("seed", [101, 202, 303])
 def test_random_sweep(seed):
     rng = np.random.default_rng(seed)
-    kinds = [_plain, _variant, _strided, _gated, _delayed, _plan]
+    kinds = [_plain, _variant, _strided, _gated, _delayed, _delayed_shift, _plan]
     for _ in range(120):
-        kind = kinds[int(rng.choice(6, p=[0.22, 0.22, 0.14, 0.14, 0.18, 0.1]))]
+        kind = kinds[int(rng.choice(7, p=[0.2, 0.2, 0.12, 0.12, 0.14, 0.12, 0.1]))]
         kind(rng, int(rng.integers(1 << 30)))
