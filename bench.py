@@ -375,6 +375,7 @@ def bench_small_n(w, steps: int, warmup: int):
     digest = kernel_source_digest(kern)
     alg = metrics.algorithmic_bytes(w.n, w.f, w.t, accumulate=False)
     gbs = alg / (r["kernel_ms"] / 1e3) / 1e9
+    copy_gbs = copy_ceiling_gbs(w.f * w.t * w.n)
     return {"workload": w.name, "n": w.n, "f": w.f, "t": w.t,
             "value": round(r["value"], 3), "unit": "TOPS",
             "ms_per_step": round(r["ms_per_step"], 5),
@@ -384,7 +385,31 @@ def bench_small_n(w, steps: int, warmup: int):
                          "variant": vname, "time_split": vsplit,
                          "kernel_ms": round(r["kernel_ms"], 5),
                          "algorithmic_bytes_per_launch": alg,
-                         "mfma_frac": round(r["kernel_tops"] / PEAK_INT8_TOPS, 4)}}
+                         "mfma_frac": round(r["kernel_tops"] / PEAK_INT8_TOPS, 4),
+                         "copy_ceiling_gbs": round(copy_gbs, 1),
+                         "frac_of_copy": round(gbs / copy_gbs, 4)}}
+
+
+def copy_ceiling_gbs(nbytes: int, reps: int = 10) -> float:
+    """A measured stream ceiling on this device: bytes moved per second (read
+    plus write) by a device-to-device copy of nbytes, best of reps."""
+    import torch
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    best = float("inf")
+    for k in range(reps + 2):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        dst.copy_(src)
+        b.record(stream)
+        b.synchronize()
+        if k >= 2:
+            best = min(best, a.elapsed_time(b))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (best / 1e3) / 1e9
 
 
 def bench_autotune(w, r):
