@@ -123,11 +123,15 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
       (row0 + 4 * l32 < n) ? (uint32_t)(row0 + 4 * l32) + (uint32_t)(half * ss) : kOob;
   const int t_stop = min(p.t_end, p.t0 + se * kStage);   // samples [t0 + sb*64, t_stop)
   // first sample of stage st and the end of its samples; in the segment mode
-  // stages past se (loaded ahead, never multiplied) are empty
+  // stages past se (loaded ahead, never multiplied) are empty. The stage loop
+  // fetches stages in increasing order, so the segment of the next one is
+  // found by moving on from the last one found.
+  int seg = 0;
   auto stage_span = [&](int st, int& first_row, int& stop) {
     if (kMode == kSegments) {
-      int k = 0;
+      int k = seg;
       while (k + 1 < sg->count && sg->stage0[k + 1] <= st) ++k;
+      seg = k;
       first_row = sg->t0[k] + (st - sg->stage0[k]) * kStage;
       stop = st < se ? sg->t_end[k] : first_row;
     } else {

@@ -91,11 +91,15 @@ __device__ __forceinline__ void tri_run(const TriParams& p, int ch, int base, in
   const uint32_t voff = (4 * lane < n) ? (uint32_t)(p.e0 + 4 * lane) : kOob;
   const int t_stop = min(p.t_end, p.t0 + se * kStage);   // samples [t0 + sb*64, t_stop)
   // first sample of stage st and the end of its samples; in the segment mode
-  // stages past se (loaded ahead, never multiplied) are empty
+  // stages past se (loaded ahead, never multiplied) are empty. The stage loop
+  // fetches stages in increasing order, so the segment of the next one is
+  // found by moving on from the last one found.
+  int seg = 0;
   auto stage_span = [&](int st, int& row0, int& stop) {
     if (kMode == kSegments) {
-      int k = 0;
+      int k = seg;
       while (k + 1 < sg->count && sg->stage0[k + 1] <= st) ++k;
+      seg = k;
       row0 = sg->t0[k] + (st - sg->stage0[k]) * kStage;
       stop = st < se ? sg->t_end[k] : row0;
     } else {
