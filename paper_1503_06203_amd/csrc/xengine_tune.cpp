@@ -10,6 +10,7 @@
 // length is within a factor of two.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -41,6 +42,7 @@ struct TuneChoice {
 
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneChoice> g_tune;
+std::atomic<int> g_tune_size{0};   // entries in g_tune: plain calls skip the lookup at 0
 
 int t_bucket(int t) {
   int b = 0;
@@ -49,22 +51,30 @@ int t_bucket(int t) {
 }
 
 // The current device's architecture name without its feature suffix
-// ("gfx950"); "none" when no device is usable.
+// ("gfx950"); "none" when no device is usable. Queried once per device (the
+// property query costs tens of microseconds).
 std::string device_arch() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static std::string cache[kMaxDevices];
   int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "none";
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev >= 0 && dev < kMaxDevices && !cache[dev].empty()) return cache[dev];
   hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-    return "none";
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "none";
   std::string a = prop.gcnArchName;
   const size_t colon = a.find(':');
   if (colon != std::string::npos) a.resize(colon);
-  return a.empty() ? "none" : a;
+  if (a.empty()) a = "none";
+  if (dev >= 0 && dev < kMaxDevices) cache[dev] = a;
+  return a;
 }
 
 }  // namespace
 
 bool tuned_choice(int n, int f, int t, int* variant, int* split) {
-  if (t < 1) return false;
+  if (t < 1 || g_tune_size.load(std::memory_order_relaxed) == 0) return false;
   const TuneKey key{device_arch(), n, f, t_bucket(t)};
   std::lock_guard<std::mutex> lock(g_tune_mu);
   auto it = g_tune.find(key);
@@ -135,6 +145,7 @@ xeng_status xeng_autotune(const uint8_t* d_in, int32_t* d_vis, int n, int f, int
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[key] = TuneChoice{best_v, best_s, best_t};
+    g_tune_size.store((int)g_tune.size());
   }
   if (tune_cache_path != nullptr) {
     std::ofstream out(tune_cache_path, std::ios::app);
@@ -171,6 +182,7 @@ xeng_status xeng_tune_load(const char* tune_cache_path, int* entries) {
     g_tune[key] = ch;                                // later lines replace earlier ones
     ++loaded;
   }
+  g_tune_size.store((int)g_tune.size());
   if (entries) *entries = loaded;
   return XENG_OK;
 }
@@ -178,6 +190,7 @@ xeng_status xeng_tune_load(const char* tune_cache_path, int* entries) {
 void xeng_tune_clear(void) {
   std::lock_guard<std::mutex> lock(xeng::g_tune_mu);
   xeng::g_tune.clear();
+  xeng::g_tune_size.store(0);
 }
 
 }  // extern "C"
