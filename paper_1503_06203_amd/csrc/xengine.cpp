@@ -96,15 +96,9 @@ const Variant kVariants[] = {
     {"small64_w8_ring16_mfma32x32x32"},   // n <= 64, n % 4 == 0, 4-byte aligned input
     {"rect128x256_tri256_w8_bf6_mfma32x32x64"},  // as 5, on bf6 operands (exact)
 };
-constexpr int kVariantTile128 = 0;
-constexpr int kVariantRetired1 = 1;
-constexpr int kVariantRetired2 = 2;
-constexpr int kVariantTri = 3;
-constexpr int kVariantTriBf6 = 4;
-constexpr int kVariantRect = 5;
-constexpr int kVariantSmall = 6;
-constexpr int kVariantRectBf6 = 7;
+using namespace xeng::variant_ids;
 constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
+static_assert(kVariantCount == kVariantRectBf6 + 1, "one table entry per variant id");
 
 // The kernel xeng_correlate uses: the triangle kernel where it applies (it
 // wastes the least MFMA work on small arrays), else the kernel of diagonal

@@ -10,6 +10,19 @@
 
 namespace xeng {
 
+// Kernel variant ids, as xeng_correlate_variant takes them (the order of the
+// name table in xengine.cpp).
+namespace variant_ids {
+constexpr int kVariantTile128 = 0;
+constexpr int kVariantRetired1 = 1;   // 128 x 256 tiles, 4 waves: refused
+constexpr int kVariantRetired2 = 2;   // 128 x 256 tiles, 8 waves: refused
+constexpr int kVariantTri = 3;
+constexpr int kVariantTriBf6 = 4;
+constexpr int kVariantRect = 5;
+constexpr int kVariantSmall = 6;
+constexpr int kVariantRectBf6 = 7;
+}  // namespace variant_ids
+
 // Record a message for xeng_last_error() and return st.
 xeng_status fail(xeng_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 // XENG_EDEVICE with the HIP error string.

@@ -110,7 +110,7 @@ xeng_status xeng_autotune(const uint8_t* d_in, int32_t* d_vis, int n, int f, int
   const int nv = xeng_variant_count();
   for (int v = 0; v < nv && st == XENG_OK; ++v) {
     for (int sp : splits) {
-      if (v == 6 && sp != 0) continue;    // the small-array kernel takes no split
+      if (v == variant_ids::kVariantSmall && sp != 0) continue;   // it takes no split
       // a variant that cannot run this job says so without enqueuing anything
       xeng_status s1 = xeng_correlate_variant(d_in, d_vis, n, f, t, 0, 0, v, sp, hip_stream);
       if (s1 == XENG_EINVAL || s1 == XENG_ENOTFOUND) break;
