@@ -28,9 +28,10 @@
  * Memory and streams: every d_ pointer is device memory owned by the caller
  * (typically allocated through PyTorch). The library never allocates or frees
  * device memory, and keeps none apart from one static array per device that
- * only xeng_plan_run_static uses (XENG_STATIC_SCRATCH_BYTES). All GPU work is enqueued on the caller's hipStream_t
- * (passed as void*, NULL = the null stream) and returns without waiting;
- * buffers must stay valid until that work completes.
+ * only xeng_plan_run_static uses (XENG_STATIC_SCRATCH_BYTES). All GPU work is
+ * enqueued on the caller's hipStream_t (passed as void*, NULL = the null
+ * stream) and returns without waiting; buffers must stay valid until that work
+ * completes.
  *
  * Errors: every call returns an xeng_status; nothing throws or aborts across
  * this boundary. xeng_last_error() returns a message for the calling thread's
@@ -331,9 +332,10 @@ void xeng_plan_destroy(xeng_plan* plan);
  * slot, one persistent-kernel step holding the oldest pending frames of every
  * job that has nothing in flight (up to 16 of a job whose accumulator already
  * holds sums, added with int32 atomic adds; only its first frame, which
- * overwrites, runs alone); frames that arrive meanwhile join later steps, and up to max_inflight steps run concurrently on the device (each on
- * a stream of its own, ordered after the work queued so far on hip_stream, the
- * stream the frames are produced on). Results are bit-identical to
+ * overwrites, runs alone); frames that arrive meanwhile join later steps, and
+ * up to max_inflight steps run concurrently on the device (each on a stream of
+ * its own, ordered after the work queued so far on hip_stream, the stream the
+ * frames are produced on). Results are bit-identical to
  * xeng_correlate over each job's frames in order.
  *
  * Admission by memory: xeng_job_open refuses (XENG_EBUSY) an accumulator that
