@@ -16,6 +16,10 @@ Prints ONE JSON line:
   cpu_baseline the CPU oracle timed on a bounded sample of the same workload
   pathfinder, tiny, small_n, time_major, gated, delayed, bf6, batched, served
                secondary measurements (other shapes and entry points)
+
+--workload runs one workload alone (for profiling): tiny, pathfinder, large_n,
+small_n, batched, served, or large_n_delayed (the large-N frame with
+per-element delays: the shift kernel, then the correlation).
 """
 from __future__ import annotations
 
@@ -221,13 +225,14 @@ def bench_gated(w, steps: int, warmup: int):
             "ms_per_step": round(wall / steps * 1e3, 5)}
 
 
-def bench_delayed(w, steps: int, warmup: int):
+def bench_delayed(w, steps: int, warmup: int, main_only: bool = False):
     """Delay compensation on the workload: per-element integer delays drawn
     uniformly from [0, 64] samples (the first element takes the largest), a
     64-sample halo in front of each channel. For comparison the same call with
     all delays equal (a shifted sample window, run on the dense kernel) and
     with delays 63 and 64 alternating (the smallest spread the window form
-    stages). The effective rate counts the frame's samples only."""
+    stages), unless main_only. The effective rate counts the frame's samples
+    only."""
     import numpy as np
     import torch
 
@@ -253,6 +258,10 @@ def bench_delayed(w, steps: int, warmup: int):
                            warmup)
     out.update({"value": round(ops / (wall / steps) / 1e12, 3), "unit": "TOPS",
                 "ms_per_step": round(wall / steps * 1e3, 5)})
+    if main_only:
+        del x, vis, ws
+        torch.cuda.empty_cache()
+        return out
     same = np.full(w.n, dmax, dtype=np.int32)     # the same input, no relative shift
     wall0, _ = time_steps(lambda: xe.correlate_delayed(x, vis, same, workspace=ws), steps, warmup)
     out["equal_delays_value"] = round(ops / (wall0 / steps) / 1e12, 3)
@@ -596,7 +605,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", default="large_n",
-                    choices=["tiny", "pathfinder", "large_n", "small_n", "batched", "served"])
+                    choices=["tiny", "pathfinder", "large_n", "small_n", "batched", "served",
+                             "large_n_delayed"])
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-reference", action="store_true",
@@ -615,19 +625,29 @@ def main():
         sys.exit(2)
     from synth import workloads
 
+    def copy_reference():
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     if args.workload in ("batched", "served"):
         r = bench_batched(args.steps, args.warmup) if args.workload == "batched" else bench_served()
+        print(json.dumps(r), flush=True)
+        return
+    if args.workload == "large_n_delayed":
+        # the delayed large-N frame alone (shift kernel, then the rect kernel)
+        r = bench_delayed(workloads.LARGE_N, args.steps, args.warmup, main_only=True)
+        if args.copy_reference:
+            copy_reference()
         print(json.dumps(r), flush=True)
         return
 
     w = workloads.WORKLOADS[args.workload]
     r = bench_workload(w, args.steps, args.warmup)
     if args.copy_reference:
-        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_reference()
     line = {
         "metric": "effective correlation TOPS (8 ops/complex MAC) + % int8 MFMA peak",
         "value": round(r["value"], 3),
