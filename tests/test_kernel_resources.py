@@ -78,3 +78,17 @@ def test_small_kernel_has_no_scratch_and_fits_lds(tmp_path):
     asm = device_asm("xcorr_small.hip", tmp_path)
     assert kernel_field(asm, "xcorr_small_kernel", "amdhsa_private_segment_fixed_size") == 0
     assert kernel_field(asm, "xcorr_small_kernel", "amdhsa_group_segment_fixed_size") <= 160 * 1024
+
+
+def test_shift_and_tile_kernels_have_no_scratch_and_fit_lds(tmp_path):
+    # the delay shift's loader waves wait on a count of their own loads, and
+    # the general tile kernel holds 128 accumulators per lane: neither may spill
+    asm = device_asm("xcorr_shift.hip", tmp_path)
+    assert kernel_field(asm, "xcorr_shift_kernel", "amdhsa_private_segment_fixed_size") == 0
+    assert kernel_field(asm, "xcorr_shift_kernel", "amdhsa_group_segment_fixed_size") <= 160 * 1024
+    asm = device_asm("xcorr_tile.hip", tmp_path)
+    blocks = re.findall(r"\.amdhsa_kernel\s+(\S*xcorr_tile128_kernel\S*)", asm)
+    assert len(blocks) == 2, blocks   # dword-aligned and byte-wise loads
+    for name in blocks:
+        assert kernel_field(asm, re.escape(name), "amdhsa_private_segment_fixed_size") == 0, name
+        assert kernel_field(asm, re.escape(name), "amdhsa_group_segment_fixed_size") <= 160 * 1024
