@@ -231,12 +231,15 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
     }
   };
 
-  // One stage st: the step-0 operands are requested first, then this wave's
-  // loads for st+2, a wait for its loads of st+1 and their transposing reads;
-  // each MFMA step then requests the next step's operands and overlaps its
-  // MFMAs with part of the decode of st+1 (into the other operand buffer).
-  // kPar = (st - sb) & 1 selects the static buffers. Stages past se are
-  // fetched and decoded as well; their rows read nothing.
+  // One stage st: the step-0 operands are requested first, then a wait for
+  // this wave's loads of st+1 (issued a stage earlier) and their transposing
+  // reads; each MFMA step then requests the next step's operands and overlaps
+  // its MFMAs with part of the decode of st+1 (into the other operand buffer).
+  // The loads of st+2 go out after the first MFMA step, so that the matrix
+  // cores start before the load instructions are issued (about 1 % faster
+  // than issuing them first). kPar = (st - sb) & 1 selects the static
+  // buffers. Stages past se are fetched and decoded as well; their rows read
+  // nothing.
   auto body = [&](auto par, int st) {
     constexpr int kPar = decltype(par)::value;
     uint8_t* const c_ld = kPar ? craw1 : craw0;
@@ -245,8 +248,7 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
     const uint8_t* const r_dc = kPar ? rraw0 : rraw1;
     Frags fr[2];
     load_frags(fr[0], kPar, 0);
-    fetch(c_ld, r_ld, st + 2);
-    vm_wait<kLoads>();   // all but the loads just issued are done: st+1 is in LDS
+    vm_wait<0>();   // this wave's loads of st+1 are in LDS
     v2i rawv[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) rawv[i] = tr_read(c_dc, r_dc, i);
@@ -261,6 +263,10 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
       }
       mfma_step(fr[ks & 1]);
       __builtin_amdgcn_sched_barrier(0);
+      if (ks == 0) {
+        fetch(c_ld, r_ld, st + 2);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
     lds_barrier();
   };
