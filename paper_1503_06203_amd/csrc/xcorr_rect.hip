@@ -139,7 +139,9 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
       stop = t_stop;
     }
   };
-  auto fetch = [&](uint8_t* craw, uint8_t* rraw, int st) {
+  // kPanels: 1 loads the column panel, 2 the row panel, 3 both
+  auto fetch = [&](uint8_t* craw, uint8_t* rraw, int st, auto panels) {
+    constexpr int kPanels = decltype(panels)::value;
     int row0_st, stop;
     stage_span(st, row0_st, stop);
     const int first = __builtin_amdgcn_readfirstlane(row0_st + 8 * wave);
@@ -147,17 +149,24 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
     const int records = bytes <= 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : (int)bytes);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(chan + (int64_t)first * ss), 0, records, 0x00020000);
+    if constexpr ((kPanels & 1) != 0) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rs, (lds_void_ptr)(craw + (8 * wave + r) * kColStride), 4,
-          voff_c + (uint32_t)(r * ss), 0, 0, 0);
+      for (int r = 0; r < 8; ++r)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (lds_void_ptr)(craw + (8 * wave + r) * kColStride), 4,
+            voff_c + (uint32_t)(r * ss), 0, 0, 0);
+    }
+    if constexpr ((kPanels & 2) != 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rs, (lds_void_ptr)(rraw + (4 * wave + q) * kPairStride), 4,
-          voff_r + (uint32_t)(2 * q * ss), 0, 0, 0);
+      for (int q = 0; q < 4; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (lds_void_ptr)(rraw + (4 * wave + q) * kPairStride), 4,
+            voff_r + (uint32_t)(2 * q * ss), 0, 0, 0);
+    }
   };
+  const std::integral_constant<int, 1> kColPanel;
+  const std::integral_constant<int, 2> kRowPanel;
+  const std::integral_constant<int, 3> kBothPanels;
 
   // ---- decode: ds_read_b64_tr_b8 over the wave's 8 rows. In each 16-lane
   // group the even lanes name the rows of elements e0..e0+7 and the odd lanes
@@ -235,9 +244,10 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
   // this wave's loads of st+1 (issued a stage earlier) and their transposing
   // reads; each MFMA step then requests the next step's operands and overlaps
   // its MFMAs with part of the decode of st+1 (into the other operand buffer).
-  // The loads of st+2 go out after the first MFMA step, so that the matrix
-  // cores start before the load instructions are issued (about 1 % faster
-  // than issuing them first). kPar = (st - sb) & 1 selects the static
+  // The loads of st+2 go out after the first MFMA step (the column panel) and
+  // the second (the row panel), so that the matrix cores start before the
+  // load instructions are issued (about 2 % faster than issuing them all
+  // first). kPar = (st - sb) & 1 selects the static
   // buffers. Stages past se are fetched and decoded as well; their rows read
   // nothing.
   auto body = [&](auto par, int st) {
@@ -264,7 +274,10 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
       mfma_step(fr[ks & 1]);
       __builtin_amdgcn_sched_barrier(0);
       if (ks == 0) {
-        fetch(c_ld, r_ld, st + 2);
+        fetch(c_ld, r_ld, st + 2, kColPanel);
+        __builtin_amdgcn_sched_barrier(0);
+      } else if (ks == 1) {
+        fetch(c_ld, r_ld, st + 2, kRowPanel);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -272,8 +285,8 @@ __device__ __forceinline__ void rect_run(const RectParams& p, int ch, int row0, 
   };
 
   // ---- prologue: fetch sb and sb+1, decode sb -------------------------------------
-  fetch(craw0, rraw0, sb);
-  fetch(craw1, rraw1, sb + 1);
+  fetch(craw0, rraw0, sb, kBothPanels);
+  fetch(craw1, rraw1, sb + 1, kBothPanels);
   vm_wait<kLoads>();
 #pragma unroll
   for (int i = 0; i < 6; ++i) decode(tr_read(craw0, rraw0, i), 0, i);
